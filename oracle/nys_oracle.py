@@ -1,0 +1,291 @@
+"""Plain CPU float64 oracle for Nystrom-preconditioned CG on kernel systems.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously correct reference
+that the GPU library is checked against.  Only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it; the library itself
+never does, and this module imports nothing from the library.
+
+What it computes (all in float64, dense, no blocking or fusion):
+
+* The regularised kernel system (K + lambda I) x = b of the section
+  "Positive-Definite Linear Systems" (eq. rlaopt-regularized-linear-system), with
+  K_ij = k(x_i, x_j) as in kernel ridge regression (eq. rlaopt-krr).  The paper
+  names no kernel; the two used here are the Gaussian RBF
+  exp(-|x-y|^2 / (2 sigma^2)) and the Laplacian exp(-|x-y|_2 / sigma) (L2 norm).
+* The direct solution by a Cholesky factorisation, the method the same section
+  names as the O(n^3) baseline.
+* The randomized Nystrom approximation the paper cites for its preconditioner
+  (section "Related Work", large-scale linear systems; its configuration is
+  table tab:rlaopt-nystrom-config).  The paper prints no steps, so the steps are
+  those of the cited method: the stabilised fixed-rank Nystrom approximation
+  (orthonormalised Gaussian test matrix, shift nu, Cholesky of the shifted core,
+  SVD of the factor, shift removed from the eigenvalues).
+* The Nystrom preconditioner P = K_hat + lambda I (damping mode "non_adaptive"
+  with base damping lambda in table tab:rlaopt-nystrom-config), applied through
+  its closed-form inverse.
+* Textbook preconditioned CG with the stopping rule of table
+  tab:rlaopt-pcg-stopping (|r_k| <= tol |b| for every right-hand side, or the
+  iteration cap), and the float64 relative residual of the common accuracy
+  check (section "Common Accuracy Checks", eq. experiment-relative-residual).
+* A validation loss through the solution and its exact gradient with respect
+  to (lambda, sigma), for the bilevel problem of eq. rlaopt-bilevel.
+
+Every function is pinned by tests that check it against closed forms, library
+routines or brute force; see the test suite for the list.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg as sla
+
+RBF = 0
+LAPLACIAN = 1
+
+
+# ---------------------------------------------------------------------------
+# Kernel matrix (eq. rlaopt-krr: K_ij = k(x_i, x_j))
+# ---------------------------------------------------------------------------
+
+def squared_distances(Xr: np.ndarray, Xc: np.ndarray) -> np.ndarray:
+    """|x_i - y_j|^2 from direct coordinate differences (not the expanded
+    |x|^2 + |y|^2 - 2 x.y form), so identical points give exactly 0."""
+    Xr = np.asarray(Xr, dtype=np.float64)
+    Xc = np.asarray(Xc, dtype=np.float64)
+    D = np.zeros((Xr.shape[0], Xc.shape[0]))
+    for l in range(Xr.shape[1]):
+        diff = Xr[:, l][:, None] - Xc[:, l][None, :]
+        D += diff * diff
+    return D
+
+
+def kernel_matrix(Xr, Xc, kind: int, sigma: float) -> np.ndarray:
+    """K(Xr, Xc) with K_ij = k(x_i, y_j)."""
+    D = squared_distances(Xr, Xc)
+    if kind == RBF:
+        return np.exp(-D / (2.0 * sigma * sigma))
+    if kind == LAPLACIAN:
+        return np.exp(-np.sqrt(D) / sigma)
+    raise ValueError("unknown kernel kind")
+
+
+def kernel_dsigma_matrix(Xr, Xc, kind: int, sigma: float) -> np.ndarray:
+    """Entrywise derivative dK/dsigma.
+    RBF:       d/ds exp(-D/(2 s^2)) = exp(-D/(2 s^2)) * D / s^3
+    Laplacian: d/ds exp(-sqrt(D)/s)  = exp(-sqrt(D)/s) * sqrt(D) / s^2
+    """
+    D = squared_distances(Xr, Xc)
+    if kind == RBF:
+        return np.exp(-D / (2.0 * sigma * sigma)) * D / sigma ** 3
+    if kind == LAPLACIAN:
+        dist = np.sqrt(D)
+        return np.exp(-dist / sigma) * dist / sigma ** 2
+    raise ValueError("unknown kernel kind")
+
+
+def kernel_matvec(Xr, Xc, V, kind: int, sigma: float, deriv: int = 0,
+                  alpha: float = 1.0, beta: float = 0.0, Out=None) -> np.ndarray:
+    """Out = alpha * K(Xr, Xc) V + beta * Out   (deriv=1: dK/dsigma in place of K)."""
+    V = np.asarray(V, dtype=np.float64)
+    M = kernel_dsigma_matrix(Xr, Xc, kind, sigma) if deriv else kernel_matrix(Xr, Xc, kind, sigma)
+    res = alpha * (M @ V)
+    if beta != 0.0:
+        res = res + beta * np.asarray(Out, dtype=np.float64)
+    return res
+
+
+def kernel_matvec_rows(Xr, Xc, V, kind: int, sigma: float, deriv: int = 0) -> np.ndarray:
+    """K(Xr, Xc) V evaluated one block of rows at a time, for row samples of
+    problems too large for a dense K: the same definition, bounded memory."""
+    out = np.empty((np.asarray(Xr).shape[0],) + np.asarray(V).shape[1:])
+    step = max(1, int(2e8 // max(1, np.asarray(Xc).shape[0])))
+    for s in range(0, out.shape[0], step):
+        out[s:s + step] = kernel_matvec(Xr[s:s + step], Xc, V, kind, sigma, deriv)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Direct solve (section "Positive-Definite Linear Systems")
+# ---------------------------------------------------------------------------
+
+def direct_solve(K: np.ndarray, b: np.ndarray, lam: float) -> np.ndarray:
+    """x* = (K + lam I)^{-1} b by Cholesky."""
+    A = K + lam * np.eye(K.shape[0])
+    c = sla.cho_factor(A, lower=True)
+    return sla.cho_solve(c, b)
+
+
+def relative_residual(K: np.ndarray, x: np.ndarray, b: np.ndarray, lam: float) -> np.ndarray:
+    """Per-column |(K + lam I) x - b|_2 / |b|_2 in float64 (eq.
+    experiment-relative-residual, with K in place of X^T X and b in place of X^T y)."""
+    x = np.asarray(x, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+        b = b[:, None]
+    res = K @ x + lam * x - b
+    nb = np.linalg.norm(b, axis=0)
+    nr = np.linalg.norm(res, axis=0)
+    return np.where(nb > 0, nr / np.where(nb > 0, nb, 1.0), nr)
+
+
+# ---------------------------------------------------------------------------
+# Randomized Nystrom approximation (the cited method; config table
+# tab:rlaopt-nystrom-config)
+# ---------------------------------------------------------------------------
+
+def float_spacing(t: float) -> float:
+    """eps(t) = 2^(floor(log2 t) - 52): the gap between t and the next float64."""
+    return float(np.spacing(np.float64(t)))
+
+
+def nystrom(apply_K, Omega: np.ndarray):
+    """Stabilised fixed-rank Nystrom approximation K_hat = U diag(lam_hat) U^T.
+
+    apply_K(V) must return K @ V.  Steps of the cited method:
+      1. Q = thin QR of the Gaussian test matrix Omega.
+      2. Y = K Q.
+      3. nu = sqrt(n) * eps(|Y|_2).
+      4. Y_nu = Y + nu Q.
+      5. C = upper Cholesky factor of (Q^T Y_nu + Y_nu^T Q) / 2.
+      6. B = Y_nu C^{-1}.
+      7. [U, S, ~] = thin SVD of B.
+      8. lam_hat = max(0, S^2 - nu).
+    Returns (U, lam_hat, nu), lam_hat in descending order.
+    """
+    n = Omega.shape[0]
+    Q, _ = np.linalg.qr(np.asarray(Omega, dtype=np.float64), mode="reduced")
+    Y = np.asarray(apply_K(Q), dtype=np.float64)
+    nu = math.sqrt(n) * float_spacing(np.linalg.norm(Y, 2))
+    Ynu = Y + nu * Q
+    core = Q.T @ Ynu
+    core = 0.5 * (core + core.T)
+    C = sla.cholesky(core, lower=False)
+    B = sla.solve_triangular(C, Ynu.T, trans="T", lower=False).T   # B C = Y_nu
+    U, S, _ = np.linalg.svd(B, full_matrices=False)
+    lam_hat = np.maximum(0.0, S * S - nu)
+    return U, lam_hat, nu
+
+
+def nystrom_matrix(U: np.ndarray, lam_hat: np.ndarray) -> np.ndarray:
+    """K_hat = U diag(lam_hat) U^T."""
+    return (U * lam_hat) @ U.T
+
+
+def precond_apply(U: np.ndarray, lam_hat: np.ndarray, lam, R: np.ndarray) -> np.ndarray:
+    """P^{-1} R for P = U diag(lam_hat) U^T + lam I, by its closed-form inverse
+    P^{-1} = U diag(1 / (lam_hat + lam)) U^T + (I - U U^T) / lam.
+    lam may be a scalar or one value per column of R."""
+    R = np.asarray(R, dtype=np.float64)
+    one = R.ndim == 1
+    if one:
+        R = R[:, None]
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (R.shape[1],))
+    W = U.T @ R
+    Z = U @ (W / (lam_hat[:, None] + lam[None, :])) + (R - U @ W) / lam[None, :]
+    return Z[:, 0] if one else Z
+
+
+# ---------------------------------------------------------------------------
+# Preconditioned CG (stopping rule of table tab:rlaopt-pcg-stopping)
+# ---------------------------------------------------------------------------
+
+def pcg(apply_A, b: np.ndarray, apply_Pinv=None, tol: float = 1e-6, max_iters: int = 1000,
+        x0: np.ndarray | None = None):
+    """Textbook preconditioned conjugate gradient for one right-hand side.
+
+    apply_A(v) = A v; apply_Pinv(r) = P^{-1} r (None: identity, i.e. plain CG).
+    Stops when |r_k|_2 <= tol |b|_2 with r_k the recursively updated residual, or
+    after max_iters products with A.  Returns (x, iterations, recursive relres).
+    b = 0 returns x = 0 after 0 iterations.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    if bnorm == 0.0:
+        return x, 0, 0.0
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    if float(np.linalg.norm(r)) <= tol * bnorm:
+        return x, 0, float(np.linalg.norm(r)) / bnorm
+    z = apply_Pinv(r) if apply_Pinv is not None else r.copy()
+    p = z.copy()
+    rho = float(r @ z)
+    it = 0
+    rel = float(np.linalg.norm(r)) / bnorm
+    while it < max_iters:
+        w = apply_A(p)
+        alpha = rho / float(p @ w)
+        x = x + alpha * p
+        r = r - alpha * w
+        it += 1
+        rel = float(np.linalg.norm(r)) / bnorm
+        if rel <= tol:
+            break
+        z = apply_Pinv(r) if apply_Pinv is not None else r.copy()
+        rho_new = float(r @ z)
+        beta = rho_new / rho
+        rho = rho_new
+        p = z + beta * p
+    return x, it, rel
+
+
+def nyspcg_dense(X, B, lambdas, kind, sigma, Omega=None, tol=1e-6, max_iters=1000):
+    """NysPCG on every column: column c uses lambdas[c // nrhs] and B[:, c % nrhs].
+    Omega None -> plain CG.  Returns (Xsol (n, nlam*nrhs), iters list, recursive relres list,
+    true FP64 relres array)."""
+    K = kernel_matrix(X, X, kind, sigma)
+    B = np.asarray(B, dtype=np.float64)
+    if B.ndim == 1:
+        B = B[:, None]
+    nrhs = B.shape[1]
+    if Omega is not None:
+        U, lam_hat, _ = nystrom(lambda V: K @ V, Omega)
+    cols, iters, rels, trues = [], [], [], []
+    for lam in lambdas:
+        for j in range(nrhs):
+            b = B[:, j]
+            Pinv = (lambda r, lam=lam: precond_apply(U, lam_hat, lam, r)) if Omega is not None else None
+            x, it, rel = pcg(lambda v, lam=lam: K @ v + lam * v, b, Pinv, tol, max_iters)
+            cols.append(x)
+            iters.append(it)
+            rels.append(rel)
+            trues.append(float(relative_residual(K, x, b, lam)[0]))
+    return np.stack(cols, axis=1), iters, rels, np.array(trues)
+
+
+# ---------------------------------------------------------------------------
+# Gradient of a validation loss through the solution (eq. rlaopt-bilevel)
+# ---------------------------------------------------------------------------
+
+def validation_loss(X, y, Xv, yv, kind, sigma, lam) -> float:
+    """L(lambda, sigma) = mean((K(Xv, X) x* - yv)^2), x* = (K(X, X) + lambda I)^{-1} y."""
+    K = kernel_matrix(X, X, kind, sigma)
+    x = direct_solve(K, np.asarray(y, dtype=np.float64).reshape(-1), lam)
+    pred = kernel_matrix(Xv, X, kind, sigma) @ x
+    res = pred - np.asarray(yv, dtype=np.float64).reshape(-1)
+    return float(res @ res) / res.shape[0]
+
+
+def validation_loss_grad(X, y, Xv, yv, kind, sigma, lam):
+    """Exact dense gradient of L with respect to (lambda, sigma).
+
+    With x* = A^{-1} y, A = K + lambda I, e = (2/n_v)(K_vt x* - y_v) and
+    a = A^{-1} K_vt^T e (the adjoint solution):
+        dL/dlambda = -a^T x*
+        dL/dsigma  = e^T (dK_vt/dsigma) x* - a^T (dK/dsigma) x*
+    Returns (L, dL/dlambda, dL/dsigma, x*, a)."""
+    y = np.asarray(y, dtype=np.float64).reshape(-1)
+    yv = np.asarray(yv, dtype=np.float64).reshape(-1)
+    K = kernel_matrix(X, X, kind, sigma)
+    x = direct_solve(K, y, lam)
+    Kvt = kernel_matrix(Xv, X, kind, sigma)
+    res = Kvt @ x - yv
+    L = float(res @ res) / res.shape[0]
+    e = (2.0 / res.shape[0]) * res
+    a = direct_solve(K, Kvt.T @ e, lam)
+    dlam = -float(a @ x)
+    dK = kernel_dsigma_matrix(X, X, kind, sigma)
+    dKvt = kernel_dsigma_matrix(Xv, X, kind, sigma)
+    dsig = float(e @ (dKvt @ x)) - float(a @ (dK @ x))
+    return L, dlam, dsig, x, a

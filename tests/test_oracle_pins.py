@@ -1,0 +1,361 @@
+"""Pins for the CPU float64 oracle (no GPU).
+
+Each test checks an oracle function against something other than itself: a
+closed form derived by hand, brute-force loops over tiny inputs, an independent
+library routine, or an invariant the mathematics fixes.  The mutation tests at
+the end plant plausible mistakes in copies of oracle functions and show that
+the corresponding pin catches them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import nys_inputs as ni
+import oracle as o
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "closed_forms.json")
+
+
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- kernel matrix
+
+def test_kernel_closed_form_triangle():
+    g = golden()["triangle_3_4_5"]
+    X = np.array([g["x"]])
+    Y = np.array([g["y"]])
+    s = g["sigma"]
+    assert o.kernel_matrix(X, Y, o.RBF, s)[0, 0] == pytest.approx(g["rbf"], rel=1e-15)
+    assert o.kernel_matrix(X, Y, o.LAPLACIAN, s)[0, 0] == pytest.approx(g["laplacian"], rel=1e-15)
+    assert o.kernel_dsigma_matrix(X, Y, o.RBF, s)[0, 0] == pytest.approx(g["rbf_dsigma"], rel=1e-14)
+    assert o.kernel_dsigma_matrix(X, Y, o.LAPLACIAN, s)[0, 0] == pytest.approx(g["laplacian_dsigma"], rel=1e-14)
+
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+def test_kernel_bruteforce_loops(kind):
+    rng = np.random.default_rng(3)
+    Xr = rng.standard_normal((5, 3))
+    Xc = rng.standard_normal((4, 3))
+    s = 1.7
+    K = o.kernel_matrix(Xr, Xc, kind, s)
+    for i in range(5):
+        for j in range(4):
+            d2 = sum((float(Xr[i, l]) - float(Xc[j, l])) ** 2 for l in range(3))
+            ref = math.exp(-d2 / (2 * s * s)) if kind == o.RBF else math.exp(-math.sqrt(d2) / s)
+            assert K[i, j] == pytest.approx(ref, rel=1e-14)
+
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+def test_kernel_special_cases(kind):
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((20, 4))
+    # identical points -> exactly 1 on the diagonal (direct differences)
+    K = o.kernel_matrix(X, X, kind, 2.0)
+    assert np.all(np.diag(K) == 1.0)
+    assert np.allclose(K, K.T, rtol=0, atol=0)
+    # sigma -> infinity: K -> 1 1^T
+    Kinf = o.kernel_matrix(X, X, kind, 1e9)
+    assert np.max(np.abs(Kinf - 1.0)) < 1e-8
+    # both kernels are positive definite on distinct points
+    assert np.linalg.eigvalsh(K).min() > 0.0
+    # sigma -> 0: K -> I
+    K0 = o.kernel_matrix(X, X, kind, 1e-3)
+    assert np.max(np.abs(K0 - np.eye(20))) < 1e-12
+
+
+def test_kernel_two_point_eigs():
+    g = golden()["two_point_eigs"]
+    K = o.kernel_matrix(np.array(g["X"]), np.array(g["X"]), o.RBF, g["sigma"])
+    assert np.allclose(np.sort(np.linalg.eigvalsh(K))[::-1], g["eigs"], rtol=1e-15)
+
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+def test_dsigma_matches_central_difference(kind):
+    rng = np.random.default_rng(5)
+    Xr = rng.standard_normal((7, 3))
+    Xc = rng.standard_normal((6, 3))
+    s, h = 1.3, 1e-5
+    fd = (o.kernel_matrix(Xr, Xc, kind, s + h) - o.kernel_matrix(Xr, Xc, kind, s - h)) / (2 * h)
+    an = o.kernel_dsigma_matrix(Xr, Xc, kind, s)
+    assert np.max(np.abs(fd - an)) <= 1e-8 * np.max(np.abs(an))
+
+
+def test_kernel_matvec_alpha_beta():
+    rng = np.random.default_rng(6)
+    Xr, Xc = rng.standard_normal((5, 2)), rng.standard_normal((8, 2))
+    V, Out = rng.standard_normal((8, 3)), rng.standard_normal((5, 3))
+    K = o.kernel_matrix(Xr, Xc, o.RBF, 1.1)
+    got = o.kernel_matvec(Xr, Xc, V, o.RBF, 1.1, 0, 2.0, -0.5, Out)
+    ref = np.einsum("ij,jk->ik", K, V) * 2.0 - 0.5 * Out
+    assert np.allclose(got, ref, rtol=1e-14, atol=1e-14)
+    rows = o.kernel_matvec_rows(Xr, Xc, V, o.RBF, 1.1)
+    assert np.allclose(rows, K @ V, rtol=1e-14)
+
+
+# ---------------------------------------------------------------- direct solve
+
+def test_direct_solve_two_point_closed_form():
+    g = golden()["two_point_solve"]
+    X = np.array(g["X"])
+    K = o.kernel_matrix(X, X, o.RBF, g["sigma"])
+    x = o.direct_solve(K, np.array(g["b"]), g["lam"])
+    assert np.allclose(x, g["x"], rtol=1e-14)
+
+
+def test_direct_solve_vs_lapack_lu():
+    w = ni.small_problem(300, 5, seed=1)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    x = o.direct_solve(K, w.B[:, 0], w.lambdas[0])
+    ref = np.linalg.solve(K + w.lambdas[0] * np.eye(300), w.B[:, 0])
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert o.relative_residual(K, x, w.B[:, 0], w.lambdas[0])[0] < 1e-13
+
+
+# ---------------------------------------------------------------- Nystrom
+
+def _spd_test_matrix(n, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.logspace(0, -math.log10(cond), n)
+    return (Q * ev) @ Q.T
+
+
+def test_nystrom_closed_form():
+    """With nu -> 0, K_hat = Y (Omega^T Y)^{-1} Y^T, Y = K Omega (invariant to
+    orthonormalising Omega)."""
+    K = _spd_test_matrix(30, 0, cond=10.0)
+    Om = np.random.default_rng(1).standard_normal((30, 10))
+    U, lh, nu = o.nystrom(lambda V: K @ V, Om)
+    Y = K @ Om
+    ref = Y @ np.linalg.solve(Om.T @ Y, Y.T)
+    assert nu < 1e-12
+    assert np.linalg.norm(o.nystrom_matrix(U, lh) - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+def test_nystrom_invariants(kind):
+    w = ni.small_problem(400, 6, seed=2, kind=kind, r=40)
+    K = o.kernel_matrix(w.X, w.X, kind, w.sigma)
+    Om = ni.gaussian_test_matrix(400, 40, 2)
+    U, lh, nu = o.nystrom(lambda V: K @ V, Om)
+    assert np.all(lh >= 0.0)
+    assert np.all(np.diff(lh) <= 0.0)
+    assert np.max(np.abs(U.T @ U - np.eye(40))) < 1e-12
+    Kh = o.nystrom_matrix(U, lh)
+    # K_hat is PSD and K - K_hat is PSD up to the shift nu
+    assert np.linalg.eigvalsh(Kh).min() >= -1e-12 * np.linalg.norm(K, 2)
+    assert np.linalg.eigvalsh(K - Kh).min() >= -nu - 1e-12 * np.linalg.norm(K, 2)
+    # the retained eigenvalues never exceed those of K (K_hat <= K)
+    ev = np.sort(np.linalg.eigvalsh(K))[::-1]
+    assert np.all(lh <= ev[:40] * (1 + 1e-12) + nu)
+
+
+def test_nystrom_exact_recovery_low_rank():
+    """A linear kernel K = X X^T of rank d <= r is recovered exactly; then the
+    preconditioner equals A and PCG converges in one iteration."""
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((120, 5))
+    K = X @ X.T
+    Om = rng.standard_normal((120, 12))
+    U, lh, nu = o.nystrom(lambda V: K @ V, Om)
+    assert np.linalg.norm(o.nystrom_matrix(U, lh) - K) <= 1e-10 * np.linalg.norm(K)
+    lam = 0.3
+    b = rng.standard_normal(120)
+    x, it, rel = o.pcg(lambda v: K @ v + lam * v, b, lambda r: o.precond_apply(U, lh, lam, r), 1e-10, 50)
+    assert it == 1
+    assert np.linalg.norm(x - np.linalg.solve(K + lam * np.eye(120), b)) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_precond_apply_is_inverse_of_khat_plus_lambda():
+    w = ni.small_problem(200, 4, seed=3, r=20)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(200, 20, 3))
+    lam = 0.7
+    Pm = o.nystrom_matrix(U, lh) + lam * np.eye(200)
+    Pinv = o.precond_apply(U, lh, lam, np.eye(200))
+    assert np.max(np.abs(Pinv - np.linalg.inv(Pm))) < 1e-10 * np.max(np.abs(np.linalg.inv(Pm)))
+    # per-column lambdas
+    lams = np.array([0.7, 2.0, 5.0])
+    R = np.random.default_rng(0).standard_normal((200, 3))
+    Z = o.precond_apply(U, lh, lams, R)
+    for c in range(3):
+        Pc = o.nystrom_matrix(U, lh) + lams[c] * np.eye(200)
+        assert np.allclose(Z[:, c], np.linalg.solve(Pc, R[:, c]), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+def test_preconditioned_spectrum_at_least_one(kind):
+    w = ni.small_problem(300, 5, seed=4, kind=kind, r=30)
+    K = o.kernel_matrix(w.X, w.X, kind, w.sigma)
+    U, lh, nu = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(300, 30, 4))
+    lam = 0.05
+    A = K + lam * np.eye(300)
+    Pinv = o.precond_apply(U, lh, lam, np.eye(300))
+    # P^{-1} A is similar to P^{-1/2} A P^{-1/2}: real spectrum
+    ev = np.sort(np.linalg.eigvals(Pinv @ A).real)
+    assert ev[0] >= 1.0 - nu / lam - 1e-9
+    assert ev[-1] <= 1.0 + np.linalg.norm(K - o.nystrom_matrix(U, lh), 2) / lam + 1e-9
+
+
+# ---------------------------------------------------------------- PCG
+
+def test_pcg_matches_cholesky_plain_workload():
+    w = ni.plain_fp64(0)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    Om = ni.gaussian_test_matrix(w.n, w.r, 0)
+    Xs, iters, rels, trues = o.nyspcg_dense(w.X, w.B, w.lambdas, w.kind, w.sigma, Om, tol=1e-10)
+    ref = o.direct_solve(K, w.B[:, 0], w.lambdas[0])
+    assert np.linalg.norm(Xs[:, 0] - ref) <= 1e-6 * np.linalg.norm(ref)
+    assert trues[0] <= 1e-9
+    # preconditioning pays: fewer iterations than plain CG
+    _, it_cg, _, _ = o.nyspcg_dense(w.X, w.B, w.lambdas, w.kind, w.sigma, None, tol=1e-10)
+    assert iters[0] < it_cg[0]
+
+
+def test_plain_cg_matches_scipy_cg():
+    w = ni.small_problem(250, 4, seed=5)
+    A = o.kernel_matrix(w.X, w.X, w.kind, w.sigma) + w.lambdas[0] * np.eye(250)
+    b = w.B[:, 0]
+    x, it, rel = o.pcg(lambda v: A @ v, b, None, 1e-12, 1000)
+    xs, info = spla.cg(A, b, rtol=1e-12, atol=0.0, maxiter=1000)
+    assert info == 0
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_pcg_iteration_bound_and_edge_cases():
+    w = ni.small_problem(300, 5, seed=6, r=30)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(300, 30, 6))
+    lam = 0.05
+    A = K + lam * np.eye(300)
+    Pinv = o.precond_apply(U, lh, lam, np.eye(300))
+    ev = np.sort(np.linalg.eigvals(Pinv @ A).real)
+    kappa = ev[-1] / ev[0]
+    tol = 1e-8
+    x, it, rel = o.pcg(lambda v: A @ v, w.B[:, 0], lambda r: o.precond_apply(U, lh, lam, r), tol, 1000)
+    bound = math.ceil(0.5 * math.sqrt(kappa) * math.log(2 / tol)) + 1
+    assert it <= bound
+    # b = 0
+    x0, it0, rel0 = o.pcg(lambda v: A @ v, np.zeros(300), None, tol, 10)
+    assert it0 == 0 and np.all(x0 == 0)
+    # iteration cap
+    _, itc, relc = o.pcg(lambda v: A @ v, w.B[:, 0], None, 1e-14, 3)
+    assert itc == 3 and relc > 1e-14
+    # K -> I (sigma tiny): A = (1 + lam) I converges in one iteration
+    Ki = o.kernel_matrix(w.X, w.X, o.RBF, 1e-4)
+    _, it1, _ = o.pcg(lambda v: Ki @ v + lam * v, w.B[:, 0], None, 1e-12, 10)
+    assert it1 == 1
+
+
+def test_pcg_residuals_are_preconditioner_orthogonal():
+    """r_i^T P^{-1} r_j = 0 for i != j in exact arithmetic (checked on a few steps)."""
+    w = ni.small_problem(150, 3, seed=7, r=10)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(150, 10, 7))
+    lam = 0.5
+    A = K + lam * np.eye(150)
+    b = w.B[:, 0]
+    rs = []
+    x = np.zeros(150); r = b.copy(); z = o.precond_apply(U, lh, lam, r); p = z.copy(); rho = r @ z
+    for _ in range(4):
+        rs.append(r.copy())
+        wv = A @ p; al = rho / (p @ wv); x = x + al * p; r = r - al * wv
+        z = o.precond_apply(U, lh, lam, r); rn = r @ z; p = z + (rn / rho) * p; rho = rn
+    G = np.array([[ri @ o.precond_apply(U, lh, lam, rj) for rj in rs] for ri in rs])
+    off = G - np.diag(np.diag(G))
+    assert np.max(np.abs(off)) <= 1e-9 * np.max(np.abs(np.diag(G)))
+
+
+def test_multi_column_lambda_grid_independent():
+    w = ni.small_problem(200, 4, seed=8, nrhs=2, r=20)
+    Om = ni.gaussian_test_matrix(200, 20, 8)
+    lams = [0.1, 1.0, 10.0]
+    Xs, iters, rels, trues = o.nyspcg_dense(w.X, w.B, lams, w.kind, w.sigma, Om, tol=1e-10)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    for c in range(6):
+        ref = o.direct_solve(K, w.B[:, c % 2], lams[c // 2])
+        assert np.linalg.norm(Xs[:, c] - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- gradient
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+def test_gradient_matches_central_differences(kind):
+    w = ni.small_problem(240, 4, seed=9, kind=kind)
+    X, y = w.X[:200], w.B[:200, 0]
+    Xv, yv = w.X[200:], w.B[200:, 0]
+    lam, sig = 0.5, 1.5
+    L, dlam, dsig, _, _ = o.validation_loss_grad(X, y, Xv, yv, kind, sig, lam)
+    h = 1e-4
+    f = lambda tl, ts: o.validation_loss(X, y, Xv, yv, kind, math.exp(ts), math.exp(tl))
+    tl, ts = math.log(lam), math.log(sig)
+    fd_l = (f(tl + h, ts) - f(tl - h, ts)) / (2 * h)
+    fd_s = (f(tl, ts + h) - f(tl, ts - h)) / (2 * h)
+    assert L == pytest.approx(f(tl, ts), rel=1e-14)
+    assert lam * dlam == pytest.approx(fd_l, rel=1e-5)
+    assert sig * dsig == pytest.approx(fd_s, rel=1e-5)
+
+
+# ---------------------------------------------------------------- inputs
+
+def test_input_recipes_shapes():
+    w = ni.plain_fp64(0)
+    assert w.X.shape == (2000, 10) and w.B.shape == (2000, 1)
+    assert np.allclose(w.X.mean(0), 0, atol=1e-12) and np.allclose(w.X.std(0), 1, atol=1e-12)
+    g = ni.batched_lambda_grid(0, n=1000)
+    assert g.B.shape == (1000, 64) and len(g.lambdas) == 8
+    assert set(np.unique(g.B)) <= {-1.0, 1.0}
+    assert g.lambdas[0] == pytest.approx(1e-7 * 1000) and g.lambdas[-1] == pytest.approx(1e-3 * 1000)
+    f = ni.matrix_free_fp32(0, n=5000)
+    assert f.X.shape == (5000, 20)
+    # the heavy-tailed column has much larger extremes than the Gaussian ones
+    assert np.abs(f.X[:, -1]).max() > 2 * np.abs(f.X[:, :-1]).max()
+
+
+# ---------------------------------------------------------------- planted mistakes
+
+def test_mutant_rbf_normalisation_is_caught():
+    g = golden()["triangle_3_4_5"]
+    def mutant(Xr, Xc, s):
+        return np.exp(-o.squared_distances(Xr, Xc) / (s * s))      # 2 sigma^2 -> sigma^2
+    got = mutant(np.array([g["x"]]), np.array([g["y"]]), g["sigma"])[0, 0]
+    assert abs(got - g["rbf"]) > 1e-3
+
+
+def test_mutant_dsigma_power_is_caught():
+    rng = np.random.default_rng(5)
+    Xr, Xc = rng.standard_normal((4, 3)), rng.standard_normal((4, 3))
+    s, h = 1.3, 1e-5
+    fd = (o.kernel_matrix(Xr, Xc, o.RBF, s + h) - o.kernel_matrix(Xr, Xc, o.RBF, s - h)) / (2 * h)
+    mutant = o.kernel_matrix(Xr, Xc, o.RBF, s) * o.squared_distances(Xr, Xc) / s ** 2
+    assert np.max(np.abs(fd - mutant)) > 1e-3 * np.max(np.abs(fd))
+
+
+def test_mutant_precond_missing_complement_is_caught():
+    w = ni.small_problem(120, 3, seed=3, r=10)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(120, 10, 3))
+    lam = 0.7
+    mutant = U @ np.diag(1.0 / (lh + lam)) @ U.T                   # dropped (I - UU^T)/lam
+    Pinv = np.linalg.inv(o.nystrom_matrix(U, lh) + lam * np.eye(120))
+    assert np.max(np.abs(mutant - Pinv)) > 1e-2 * np.max(np.abs(Pinv))
+
+
+def test_mutant_gradient_sign_is_caught():
+    w = ni.small_problem(140, 3, seed=11)
+    X, y, Xv, yv = w.X[:120], w.B[:120, 0], w.X[120:], w.B[120:, 0]
+    lam, sig = 0.5, 1.2
+    _, dlam, _, x, a = o.validation_loss_grad(X, y, Xv, yv, o.RBF, sig, lam)
+    h = 1e-4
+    fd = (o.validation_loss(X, y, Xv, yv, o.RBF, sig, lam * math.exp(h))
+          - o.validation_loss(X, y, Xv, yv, o.RBF, sig, lam * math.exp(-h))) / (2 * h)
+    mutant = +float(a @ x)                                           # sign flipped
+    assert abs(lam * mutant - fd) > 1e-3 * abs(fd)
+    assert abs(lam * dlam - fd) <= 1e-5 * abs(fd)
