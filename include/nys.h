@@ -1,0 +1,247 @@
+/*
+ * nys.h -- C ABI of libnys: Nystrom-preconditioned conjugate gradient (NysPCG)
+ * for kernel systems (K + lambda I) x = b on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the regularised positive-definite system of the paper's
+ * section "Positive-Definite Linear Systems" (eq. rlaopt-regularized-linear-system)
+ * with K the kernel matrix of kernel ridge regression (eq. rlaopt-krr),
+ * K_ij = k(x_i, x_j), evaluated on the fly and never stored.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers unless marked "host".  Matrices are
+ *    row-major and dense (a row of an n x m matrix is m contiguous elements).
+ *  - All arrays are owned by the caller.  The library never allocates device
+ *    memory for them, never frees them and keeps no pointer after returning.
+ *  - Scratch memory is passed in as (ws, ws_bytes): a device buffer of at
+ *    least the size nys_workspace_bytes() reports for the same arguments,
+ *    aligned to 256 bytes.  Its contents on entry are irrelevant.
+ *  - `stream` is a hipStream_t (NULL: the null stream).  Work is enqueued on
+ *    it; entry points that return host values or host-side decisions
+ *    (status of a factorisation, convergence) synchronise that stream.
+ *  - Return value: NYS_OK (0), NYS_NOT_CONVERGED (1, not an error: outputs
+ *    are valid) or a negative error code.  Nothing aborts and no C++
+ *    exception crosses this boundary.  nys_last_error() describes the last
+ *    non-zero status of the calling thread.
+ *  - Calls on different streams with disjoint buffers may run concurrently.
+ *
+ * Kernels (the paper names the kernel function k but not its form):
+ *    NYS_RBF        k(x, y) = exp(-|x - y|_2^2 / (2 sigma^2))
+ *    NYS_LAPLACIAN  k(x, y) = exp(-|x - y|_2 / sigma)        (Euclidean norm)
+ *
+ * Precisions of the kernel product K V:
+ *    NYS_FP64    distances, exponentials and accumulation in float64.
+ *    NYS_FP32    float32 MFMA distance products, float32 exp2, float32 accumulation.
+ *    NYS_BF16X3  bfloat16 split-precision distance products: each operand
+ *                a = a_hi + a_lo (round-to-nearest-even bfloat16 parts) and
+ *                a.b ~ a_hi.b_hi + a_hi.b_lo + a_lo.b_hi on MFMA with float32
+ *                accumulation; for m >= 16 columns the product with V uses the
+ *                same three-term split.  About 16 significant bits per product.
+ */
+#ifndef NYS_H
+#define NYS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define NYS_OK             0
+#define NYS_NOT_CONVERGED  1   /* iteration cap reached; outputs valid, info filled */
+#define NYS_EINVAL        (-1) /* invalid argument (null pointer, size, sigma <= 0,
+                                  lambda <= 0, tol <= 0, unsupported kind/precision) */
+#define NYS_ENOTPD        (-2) /* shifted Cholesky of the sketch core failed after
+                                  all shift retries, or PCG breakdown (p^T A p <= 0) */
+#define NYS_ENUMERIC      (-3) /* NaN or Inf in inputs or in PCG scalars */
+#define NYS_EHIP          (-4) /* HIP runtime error */
+#define NYS_ENOMEM        (-5) /* workspace smaller than nys_workspace_bytes() */
+
+typedef enum { NYS_RBF = 0, NYS_LAPLACIAN = 1 } nys_kind;
+typedef enum { NYS_FP64 = 0, NYS_FP32 = 1, NYS_BF16X3 = 2 } nys_prec;
+
+/* Operations whose workspace can be queried. */
+typedef enum {
+  NYS_OP_KERNEL_MATVEC = 0,
+  NYS_OP_SKETCH = 1,
+  NYS_OP_PRECOND_BUILD = 2,
+  NYS_OP_PRECOND_APPLY = 3,
+  NYS_OP_SOLVE = 4,
+  NYS_OP_BACKWARD = 5
+} nys_op;
+
+/* Kernel function: kind (nys_kind) and bandwidth sigma > 0. */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double sigma;
+} nys_kernel;
+
+/* Nystrom preconditioner P = U diag(lam_hat) U^T + lambda I (damping mode
+ * "non_adaptive" with base damping lambda, table tab:rlaopt-nystrom-config).
+ * The caller allocates the buffers; nys_precond_build fills them.
+ *    n        number of points (rows of U)
+ *    r        sketch size = columns of U (rank_init of the paper's NystromConfig)
+ *    rank     out: columns of U kept (those with sigma_i^2 > 1e-14 sigma_1^2);
+ *             dropped columns of U are zero and their lam_hat is 0
+ *    U        device, n x r float64, orthonormal columns
+ *    U32      device, n x r float32 copy of U, or NULL (needed by the FP32 and
+ *             BF16X3 solves)
+ *    lam_hat  device, r float64, descending, >= 0
+ *    nu       out: the shift used by the stabilised approximation
+ */
+typedef struct {
+  int64_t n;
+  int32_t r;
+  int32_t rank;
+  double *U;
+  float *U32;
+  double *lam_hat;
+  double nu;
+} nys_precond;
+
+/* PCG options (PCGStoppingCriteria, table tab:rlaopt-pcg-stopping, plus the
+ * precision controls of this library).
+ *    tol           relative residual target: column c stops when
+ *                  |r_c|_2 <= tol |b_c|_2 (default of the paper: 1e-6)
+ *    max_iters     cap on products with A per column (paper default 1000)
+ *    prec          nys_prec of the kernel product and of the CG vectors
+ *                  (FP64: float64 vectors; FP32/BF16X3: float32 vectors)
+ *    refine_every  FP32/BF16X3 only: every refine_every iterations the solution
+ *                  is accumulated in float64 and the residual b - (K + lambda I) x
+ *                  is recomputed with the float64 kernel product; 0 = only when
+ *                  a column's recursive residual meets tol
+ *    refine_mode   0: keep the search direction after a refinement (residual
+ *                  replacement); 1: restart the recurrence (p = z)
+ *    check_true    1: after the solve compute the float64 true relative residual
+ *                  of every column into info (eq. experiment-relative-residual)
+ *    max_refinements  cap on refinements per column (0: 50)
+ */
+typedef struct {
+  double tol;
+  int32_t max_iters;
+  int32_t prec;
+  int32_t refine_every;
+  int32_t refine_mode;
+  int32_t check_true;
+  int32_t max_refinements;
+} nys_pcg_opts;
+
+/* Per-column result. */
+typedef struct {
+  int32_t iters;            /* products with A after set-up */
+  int32_t refinements;      /* float64 residual recomputations */
+  int32_t status;           /* NYS_OK or NYS_NOT_CONVERGED */
+  int32_t reserved;
+  double relres_recursive;  /* |r_k| / |b| of the recurrence when it stopped */
+  double relres_true;       /* float64 |b - (K + lambda I) x| / |b| (check_true or refinement), else -1 */
+} nys_col_info;
+
+/* Workspace size for an operation.  Unused size arguments may be 0.
+ *   KERNEL_MATVEC: n = nr, n2 = nc, d, m, prec
+ *   SKETCH:        n, d, r, prec
+ *   PRECOND_BUILD: n, r
+ *   PRECOND_APPLY: n, r, m, prec
+ *   SOLVE:         n, d, r (0 if no preconditioner), m = nlam * nrhs, prec
+ *   BACKWARD:      n, d, r, prec
+ * Returns NYS_OK and *bytes, or NYS_EINVAL. */
+int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_t r, int32_t m,
+                            int32_t prec, size_t *bytes);
+
+/* kernel_matvec: Out = alpha * K(Xr, Xc) V + beta * Out, or with deriv = 1 the
+ * entrywise derivative dK/dsigma in place of K (RBF: k d^2 / sigma^3;
+ * Laplacian: k d / sigma^2).  This is the matrix-free operator product the
+ * paper applies inside CG (section "Positive-Definite Linear Systems": O(n^2)
+ * work per CG iteration) and its sketch product (the preconditioner build).
+ *    Xr   device float64 nr x d (row points, rows of K)
+ *    Xc   device float64 nc x d (column points); Xr == Xc with nr == nc marks a
+ *         symmetric product and K_ii is taken as exactly 1
+ *    V    device nc x m, float64 if prec == NYS_FP64 else float32
+ *    Out  device nr x m, same type as V; not read when beta == 0
+ * Coordinates are centred on the column mean of Xc (distances are unchanged).
+ * d must be <= 62 (FP32/FP64) or <= 82 (BF16X3). */
+int32_t kernel_matvec(nys_kernel k, int32_t deriv, int32_t prec,
+                      const double *Xr, int64_t nr, const double *Xc, int64_t nc, int32_t d,
+                      const void *V, int32_t m, void *Out, double alpha, double beta,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* nys_sketch: the sketch Y = K Q of the randomized Nystrom approximation (the
+ * preconditioner the paper cites in "Related Work", configured by table
+ * tab:rlaopt-nystrom-config).
+ *    X      device float64 n x d
+ *    Omega  device float64 n x r, in: standard Gaussian test matrix (drawn by
+ *           the caller); out: overwritten by Q, its orthonormalisation
+ *           (Q = Omega L^{-T}, L L^T = Omega^T Omega)
+ *    Y      device float64 n x r, out: K Q computed with the precision prec
+ * Requires 1 <= r <= n and r <= 1024. */
+int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32_t d,
+                   double *Omega, int32_t r, double *Y, void *ws, size_t ws_bytes, void *stream);
+
+/* nys_precond_build: stabilised fixed-rank Nystrom approximation from the
+ * sketch, all in float64 on the device:
+ *    nu = max(sqrt(n) 2^-52 |Y|_F, c_prec |Y|_F / sqrt(r)), Y_nu = Y + nu Q,
+ *    L L^T = (Q^T Y_nu + Y_nu^T Q) / 2 (retried with nu *= 10 up to 5 times),
+ *    B = Y_nu L^{-T}, B^T B = V S^2 V^T (Jacobi), U = B V S^{-1},
+ *    lam_hat = max(0, S^2 - nu), descending.
+ *    sketch_prec  the precision Y was computed in (sets c_prec: 0 for FP64,
+ *                 2^-21 FP32, 2^-14 BF16X3: the sketch error the shift must cover)
+ *    P      in: n, r, U, U32 (nullable), lam_hat buffers; out: filled, rank, nu.
+ * Returns NYS_ENOTPD if the shifted core never factors. */
+int32_t nys_precond_build(const double *Y, const double *Q, int64_t n, int32_t r, int32_t sketch_prec,
+                          nys_precond *P, void *ws, size_t ws_bytes, void *stream);
+
+/* nys_precond_apply: Z = P_c^{-1} R for every column c, with
+ * P_c = U diag(lam_hat) U^T + lambdas[c] I, through the closed form
+ * P_c^{-1} = U diag(1/(lam_hat + lambda_c)) U^T + (I - U U^T) / lambda_c.
+ *    lambdas  device float64, m values (lambda_c > 0)
+ *    R, Z     device n x m; float64 if prec == NYS_FP64 (uses U), else float32
+ *             (uses U32)
+ * R and Z must not overlap. */
+int32_t nys_precond_apply(const nys_precond *P, const double *lambdas, int32_t prec,
+                          const void *R, int32_t m, void *Z, void *ws, size_t ws_bytes, void *stream);
+
+/* nyspcg_solve: NysPCG (or plain CG when P == NULL) on nlam * nrhs independent
+ * columns sharing one kernel matrix and one preconditioner: column
+ * c = l * nrhs + j solves (K + lambdas[l] I) x = B[:, j].  Each column stops on
+ * its own when |r_c| <= tol |b_c| (table tab:rlaopt-pcg-stopping: the criterion
+ * must hold for every right-hand side) or at max_iters.  x0 = 0.  A column with
+ * b = 0 returns x = 0 after 0 iterations.
+ *    X        device float64 n x d
+ *    B        device float64 n x nrhs
+ *    lambdas  HOST float64, nlam values > 0
+ *    P        NULL (plain CG) or a built preconditioner for the same X
+ *    Xsol     device float64 n x (nlam * nrhs), out
+ *    info     HOST, nlam * nrhs entries, out
+ * Returns NYS_OK if every column converged, NYS_NOT_CONVERGED otherwise. */
+int32_t nyspcg_solve(nys_kernel k, const double *X, int64_t n, int32_t d,
+                     const double *B, int32_t nrhs, const double *lambdas, int32_t nlam,
+                     const nys_precond *P, const nys_pcg_opts *opts,
+                     double *Xsol, nys_col_info *info, void *ws, size_t ws_bytes, void *stream);
+
+/* nyspcg_backward: adjoint of x* = (K + lambda I)^{-1} b for the bilevel problem
+ * of eq. rlaopt-bilevel.  Given gx = dL/dx*, solves (K + lambda I) a = gx with the
+ * same preconditioner (a = dL/db) and returns
+ *    dL/dlambda = -a^T x*,   dL/dsigma = -a^T (dK/dsigma) x*.
+ *    xsol, gx  device float64 n (one column)
+ *    adj       device float64 n, out
+ *    dL_dlambda, dL_dsigma  HOST, out
+ *    info      HOST, one entry, out (the adjoint solve) */
+int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, double lambda,
+                        const double *xsol, const double *gx, const nys_precond *P,
+                        const nys_pcg_opts *opts, double *adj, double *dL_dlambda,
+                        double *dL_dsigma, nys_col_info *info, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Thread-local description of the last non-zero status ("" if none). */
+const char *nys_last_error(void);
+
+/* Library version string. */
+const char *nys_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NYS_H */

@@ -1,0 +1,306 @@
+"""Python binding of libnys: Nystrom-preconditioned CG for kernel systems
+(K + lambda I) x = b on an AMD Instinct MI355X.
+
+The functions below carry the names of the C ABI (include/nys.h) and only
+marshal arguments: every step runs in the HIP kernels of libnys.so.  PyTorch
+supplies device memory (tensors, workspaces) and the current HIP stream.
+There is no CPU fallback: if libnys.so is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnys.so")
+
+RBF, LAPLACIAN = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
+PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3"}
+PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
+
+OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
+OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BACKWARD = range(6)
+
+EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "nys_sketch", "nys_precond_build",
+           "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_last_error", "nys_version")
+
+c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class NysKernel(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("reserved", c_i32), ("sigma", c_f64)]
+
+
+class NysPrecondC(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("r", c_i32), ("rank", c_i32), ("U", c_vp), ("U32", c_vp),
+                ("lam_hat", c_vp), ("nu", c_f64)]
+
+
+class NysPCGOpts(ctypes.Structure):
+    _fields_ = [("tol", c_f64), ("max_iters", c_i32), ("prec", c_i32), ("refine_every", c_i32),
+                ("refine_mode", c_i32), ("check_true", c_i32), ("max_refinements", c_i32)]
+
+
+class NysColInfo(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("refinements", c_i32), ("status", c_i32), ("reserved", c_i32),
+                ("relres_recursive", c_f64), ("relres_true", c_f64)]
+
+
+class NysError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libnys error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libnys.so (built by paper_2609_08136_amd.build); raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libnys.so not found at {p}: build it with `python -m paper_2609_08136_amd.build`")
+    lib = ctypes.CDLL(p)
+    lib.nys_last_error.restype = ctypes.c_char_p
+    lib.nys_version.restype = ctypes.c_char_p
+    lib.nys_workspace_bytes.argtypes = [c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]
+    lib.kernel_matvec.argtypes = [NysKernel, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp,
+                                  c_f64, c_f64, c_vp, c_sz, c_vp]
+    lib.nys_sketch.argtypes = [NysKernel, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp, c_vp, c_sz, c_vp]
+    lib.nys_precond_build.argtypes = [c_vp, c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(NysPrecondC), c_vp, c_sz, c_vp]
+    lib.nys_precond_apply.argtypes = [ctypes.POINTER(NysPrecondC), c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_sz, c_vp]
+    lib.nyspcg_solve.argtypes = [NysKernel, c_vp, c_i64, c_i32, c_vp, c_i32, ctypes.POINTER(c_f64), c_i32,
+                                 ctypes.POINTER(NysPrecondC), ctypes.POINTER(NysPCGOpts), c_vp,
+                                 ctypes.POINTER(NysColInfo), c_vp, c_sz, c_vp]
+    lib.nyspcg_backward.argtypes = [NysKernel, c_vp, c_i64, c_i32, c_f64, c_vp, c_vp, ctypes.POINTER(NysPrecondC),
+                                    ctypes.POINTER(NysPCGOpts), c_vp, ctypes.POINTER(c_f64), ctypes.POINTER(c_f64),
+                                    ctypes.POINTER(NysColInfo), c_vp, c_sz, c_vp]
+    for name in ("kernel_matvec", "nys_sketch", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
+                 "nyspcg_backward", "nys_workspace_bytes"):
+        getattr(lib, name).restype = c_i32
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().nys_version().decode()
+
+
+def _check(rc: int, allow_not_converged: bool = True) -> int:
+    if rc == OK or (rc == NOT_CONVERGED and allow_not_converged):
+        return rc
+    raise NysError(rc, load().nys_last_error().decode())
+
+
+def _need_cuda(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major)")
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def nys_workspace_bytes(op: int, n: int, n2: int = 0, d: int = 0, r: int = 0, m: int = 0, prec: int = FP64) -> int:
+    b = c_sz(0)
+    _check(load().nys_workspace_bytes(op, n, n2, d, r, m, prec, ctypes.byref(b)))
+    return int(b.value)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _vdtype(prec: int):
+    return torch.float64 if prec == FP64 else torch.float32
+
+
+def kernel_matvec(Xr, Xc, V, kind: int, sigma: float, prec: int = FP64, deriv: int = 0, alpha: float = 1.0,
+                  beta: float = 0.0, out=None):
+    """Out = alpha K(Xr, Xc) V + beta Out  (deriv=1: dK/dsigma).  Xr, Xc float64 (n x d);
+    V, Out float64 for FP64 else float32.  V may be 1-D (one column)."""
+    lib = load()
+    _need_cuda(Xr, torch.float64, "Xr")
+    _need_cuda(Xc, torch.float64, "Xc")
+    vec = V.dim() == 1
+    V2 = V.reshape(-1, 1) if vec else V
+    _need_cuda(V2, _vdtype(prec), "V")
+    nr, d = Xr.shape
+    nc = Xc.shape[0]
+    if Xc.shape[1] != d or V2.shape[0] != nc:
+        raise ValueError("shape mismatch")
+    m = V2.shape[1]
+    if out is None:
+        out = torch.empty((nr, m), dtype=V2.dtype, device=V2.device)
+        beta = 0.0
+    out2 = out.reshape(nr, m)
+    _need_cuda(out2, _vdtype(prec), "Out")
+    ws = _workspace(nys_workspace_bytes(OP_KERNEL_MATVEC, nr, nc, d, 0, m, prec), Xr.device)
+    rc = lib.kernel_matvec(NysKernel(kind, 0, float(sigma)), int(deriv), int(prec), Xr.data_ptr(), nr, Xc.data_ptr(),
+                           nc, d, V2.data_ptr(), m, out2.data_ptr(), float(alpha), float(beta), ws.data_ptr(),
+                           ws.numel(), _stream())
+    _check(rc, allow_not_converged=False)
+    return out.reshape(-1) if vec else out
+
+
+@dataclass
+class Preconditioner:
+    """Nystrom preconditioner P = U diag(lam_hat) U^T + lambda I (buffers on the device)."""
+    U: torch.Tensor
+    U32: torch.Tensor | None
+    lam_hat: torch.Tensor
+    rank: int = 0
+    nu: float = 0.0
+
+    @property
+    def n(self) -> int:
+        return self.U.shape[0]
+
+    @property
+    def r(self) -> int:
+        return self.U.shape[1]
+
+    def c_struct(self) -> NysPrecondC:
+        return NysPrecondC(self.n, self.r, self.rank, self.U.data_ptr(),
+                           self.U32.data_ptr() if self.U32 is not None else None,
+                           self.lam_hat.data_ptr(), self.nu)
+
+
+def nys_sketch(X, Omega, kind: int, sigma: float, prec: int = FP64):
+    """Y = K Q with Q the orthonormalised Omega (Omega is overwritten by Q)."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    _need_cuda(Omega, torch.float64, "Omega")
+    n, d = X.shape
+    r = Omega.shape[1]
+    if Omega.shape[0] != n:
+        raise ValueError("Omega must have n rows")
+    Y = torch.empty((n, r), dtype=torch.float64, device=X.device)
+    ws = _workspace(nys_workspace_bytes(OP_SKETCH, n, 0, d, r, 0, prec), X.device)
+    rc = lib.nys_sketch(NysKernel(kind, 0, float(sigma)), int(prec), X.data_ptr(), n, d, Omega.data_ptr(), r,
+                        Y.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, allow_not_converged=False)
+    return Y
+
+
+def nys_precond_build(Y, Q, sketch_prec: int = FP64, with_fp32: bool = True) -> Preconditioner:
+    lib = load()
+    _need_cuda(Y, torch.float64, "Y")
+    _need_cuda(Q, torch.float64, "Q")
+    n, r = Y.shape
+    P = Preconditioner(torch.empty((n, r), dtype=torch.float64, device=Y.device),
+                       torch.empty((n, r), dtype=torch.float32, device=Y.device) if with_fp32 else None,
+                       torch.empty(r, dtype=torch.float64, device=Y.device))
+    cs = P.c_struct()
+    ws = _workspace(nys_workspace_bytes(OP_PRECOND_BUILD, n, 0, 0, r, 0, FP64), Y.device)
+    rc = lib.nys_precond_build(Y.data_ptr(), Q.data_ptr(), n, r, int(sketch_prec), ctypes.byref(cs), ws.data_ptr(),
+                               ws.numel(), _stream())
+    _check(rc, allow_not_converged=False)
+    P.rank = int(cs.rank)
+    P.nu = float(cs.nu)
+    return P
+
+
+def nys_precond_apply(P: Preconditioner, lambdas, R, prec: int = FP64):
+    """Z = P_c^{-1} R column by column (lambdas: float64 CUDA tensor, one per column)."""
+    lib = load()
+    vec = R.dim() == 1
+    R2 = R.reshape(-1, 1) if vec else R
+    _need_cuda(R2, _vdtype(prec), "R")
+    m = R2.shape[1]
+    lam = lambdas if isinstance(lambdas, torch.Tensor) else torch.tensor(lambdas, dtype=torch.float64,
+                                                                         device=R.device)
+    lam = lam.reshape(-1)
+    if lam.numel() == 1 and m > 1:
+        lam = lam.expand(m).contiguous()
+    _need_cuda(lam, torch.float64, "lambdas")
+    Z = torch.empty_like(R2)
+    ws = _workspace(nys_workspace_bytes(OP_PRECOND_APPLY, P.n, 0, 0, P.r, m, prec), R.device)
+    cs = P.c_struct()
+    rc = lib.nys_precond_apply(ctypes.byref(cs), lam.data_ptr(), int(prec), R2.data_ptr(), m, Z.data_ptr(),
+                               ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, allow_not_converged=False)
+    return Z.reshape(-1) if vec else Z
+
+
+def _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements) -> NysPCGOpts:
+    return NysPCGOpts(float(tol), int(max_iters), int(prec), int(refine_every), int(refine_mode), int(check_true),
+                      int(max_refinements))
+
+
+def _info_list(arr, count):
+    return [dict(iters=arr[i].iters, refinements=arr[i].refinements, status=arr[i].status,
+                 relres_recursive=arr[i].relres_recursive, relres_true=arr[i].relres_true) for i in range(count)]
+
+
+def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | None = None, tol: float = 1e-6,
+                 max_iters: int = 1000, prec: int = FP64, refine_every: int = -1, refine_mode: int = 0,
+                 check_true: bool = False, max_refinements: int = 0, workspace: torch.Tensor | None = None):
+    """Solve (K + lambdas[l] I) x = B[:, j] for every (l, j); column l*nrhs + j of the result.
+    Returns (Xsol (n x nlam*nrhs float64), info list, status)."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    vec = B.dim() == 1
+    B2 = B.reshape(-1, 1) if vec else B
+    _need_cuda(B2, torch.float64, "B")
+    n, d = X.shape
+    nrhs = B2.shape[1]
+    lams = [float(v) for v in (lambdas if hasattr(lambdas, "__len__") else [lambdas])]
+    nlam = len(lams)
+    m = nlam * nrhs
+    Xsol = torch.empty((n, m), dtype=torch.float64, device=X.device)
+    info = (NysColInfo * m)()
+    lam_arr = (c_f64 * nlam)(*lams)
+    need = nys_workspace_bytes(OP_SOLVE, n, 0, d, P.r if P is not None else 0, m, prec)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements)
+    cs = P.c_struct() if P is not None else None
+    rc = lib.nyspcg_solve(NysKernel(kind, 0, float(sigma)), X.data_ptr(), n, d, B2.data_ptr(), nrhs, lam_arr, nlam,
+                          ctypes.byref(cs) if cs is not None else None, ctypes.byref(o), Xsol.data_ptr(), info,
+                          ws.data_ptr(), ws.numel(), _stream())
+    _check(rc)
+    return (Xsol.reshape(-1) if (vec and nlam == 1) else Xsol), _info_list(info, m), rc
+
+
+def nyspcg_backward(X, lam: float, xsol, gx, kind: int, sigma: float, P: Preconditioner | None = None,
+                    tol: float = 1e-10, max_iters: int = 1000, prec: int = FP64, refine_every: int = -1,
+                    refine_mode: int = 0, check_true: bool = False, max_refinements: int = 0):
+    """Adjoint solve (K + lam I) a = gx; returns (a, dL/dlambda, dL/dsigma, info)."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    xs = xsol.reshape(-1).contiguous()
+    g = gx.reshape(-1).contiguous()
+    _need_cuda(xs, torch.float64, "xsol")
+    _need_cuda(g, torch.float64, "gx")
+    n, d = X.shape
+    adj = torch.empty(n, dtype=torch.float64, device=X.device)
+    dl, ds = c_f64(0.0), c_f64(0.0)
+    info = (NysColInfo * 1)()
+    ws = _workspace(nys_workspace_bytes(OP_BACKWARD, n, 0, d, P.r if P is not None else 0, 1, prec), X.device)
+    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements)
+    cs = P.c_struct() if P is not None else None
+    rc = lib.nyspcg_backward(NysKernel(kind, 0, float(sigma)), X.data_ptr(), n, d, float(lam), xs.data_ptr(),
+                             g.data_ptr(), ctypes.byref(cs) if cs is not None else None, ctypes.byref(o),
+                             adj.data_ptr(), ctypes.byref(dl), ctypes.byref(ds), info, ws.data_ptr(), ws.numel(),
+                             _stream())
+    _check(rc)
+    return adj, float(dl.value), float(ds.value), _info_list(info, 1)[0]
+
+
+def build_preconditioner(X, Omega, kind: int, sigma: float, sketch_prec: int = FP64, with_fp32: bool = True):
+    """Sketch then build: returns the preconditioner (Omega is overwritten by its orthonormalisation)."""
+    Y = nys_sketch(X, Omega, kind, sigma, sketch_prec)
+    P = nys_precond_build(Y, Omega, sketch_prec, with_fp32)
+    del Y
+    return P

@@ -1,0 +1,805 @@
+// C ABI of libnys: argument checking, workspace planning and the host-side
+// orchestration of the device kernels (sketch, preconditioner build/apply,
+// the PCG driver with column compaction and float64 refinement, backward).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcg.h"
+
+namespace nys {
+static thread_local std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+const char *last_error_cstr() { return g_err.c_str(); }
+}  // namespace nys
+
+using namespace nys;
+
+namespace {
+
+typedef unsigned short bf16bits;
+
+hipStream_t as_stream(void *p) { return reinterpret_cast<hipStream_t>(p); }
+
+int32_t einval(const std::string &m) {
+  set_error(m);
+  return NYS_EINVAL;
+}
+bool valid_prec(int p) { return p == NYS_FP64 || p == NYS_FP32 || p == NYS_BF16X3; }
+int max_dim(int prec) { return prec == NYS_BF16X3 ? 82 : 62; }
+size_t elem_bytes(int prec) { return prec == NYS_FP64 ? 8 : 4; }
+
+int32_t check_kernel(const nys_kernel &k) {
+  if (!(k.kind == NYS_RBF || k.kind == NYS_LAPLACIAN)) return einval("unknown kernel kind");
+  if (!(k.sigma > 0.0) || !std::isfinite(k.sigma)) return einval("sigma must be positive and finite");
+  return NYS_OK;
+}
+
+int32_t check_ws(const Arena &a) {
+  if (a.overflowed()) {
+    set_error("workspace smaller than nys_workspace_bytes() for these arguments");
+    return NYS_ENOMEM;
+  }
+  return NYS_OK;
+}
+
+// ------------------------------------------------------------ kernel product buffers
+struct KmvBufs {
+  double *mu = nullptr, *mpart = nullptr;
+  Packed rows, cols;
+  void *partial = nullptr, *vhi = nullptr, *vlo = nullptr;
+};
+
+void plan_points(Packed &p, int64_t n, int d, int prec, Arena &ws) {
+  p.n = n;
+  p.n_pad = round_up(std::max<int64_t>(n, 1), ROW_PAD);
+  p.Kp = packed_kp(d, prec);
+  p.prec = prec;
+  p.data = ws.take<char>((size_t)p.n_pad * p.Kp * packed_elem_bytes(prec));
+}
+
+// Points packed once; scratch reserved for every column count in [m_lo, m_max]
+// (the solver shrinks its column count as columns converge).
+void plan_kmv(KmvBufs &b, int64_t nr, int64_t nc, int d, int m_lo, int m_max, int prec, Arena &ws) {
+  b.mu = ws.take<double>(d);
+  b.mpart = ws.take<double>(col_mean_partial_elems(nc, d));
+  plan_points(b.rows, nr, d, prec, ws);
+  plan_points(b.cols, nc, d, prec, ws);
+  size_t pb = 0, ve = 0, a = 0, e = 0;
+  for (int m = std::max(1, m_lo); m <= m_max; ++m) {
+    KmvPlan p = kmv_plan(nr, nc, m, prec, b.rows.Kp);
+    kmv_scratch_sizes(p, nr, nc, m, prec, &a, &e);
+    pb = std::max(pb, a);
+    ve = std::max(ve, e);
+  }
+  // the derivative product runs in chunks of <= 4 columns with the 4-column plan
+  const KmvPlan p4 = kmv_plan(nr, nc, 4, prec, b.rows.Kp);
+  kmv_scratch_sizes(p4, nr, nc, std::min(4, std::max(1, m_max)), prec, &a, &e);
+  pb = std::max(pb, a);
+  b.partial = pb ? ws.take<char>(pb) : nullptr;
+  b.vhi = ve ? ws.take<bf16bits>(ve) : nullptr;
+  b.vlo = ve ? ws.take<bf16bits>(ve) : nullptr;
+}
+
+int32_t prep_points(KmvBufs &b, const nys_kernel &k, int prec, const double *Xr, const double *Xc,
+                    int d, hipStream_t s) {
+  NYS_RETURN_IF(launch_col_mean(Xc, b.cols.n, d, b.mu, b.mpart, s));
+  NYS_RETURN_IF(launch_pack(Xr, b.rows.n, d, b.mu, k, prec, SIDE_ROW, &b.rows, s));
+  NYS_RETURN_IF(launch_pack(Xc, b.cols.n, d, b.mu, k, prec, SIDE_COL, &b.cols, s));
+  return NYS_OK;
+}
+
+// Out = alpha K V + beta Out for m columns (ldv / ldo strides), planned for m.
+int32_t run_kmv(KmvBufs &b, const nys_kernel &k, int deriv, int prec, int same, const void *V, int m,
+                int ldv, void *Out, int ldo, double alpha, double beta, hipStream_t s) {
+  if (m <= 0) return NYS_OK;
+  const size_t eb = elem_bytes(prec);
+  if (deriv && m > 1) {
+    const KmvPlan p = kmv_plan(b.rows.n, b.cols.n, 4, prec, b.rows.Kp);
+    for (int c0 = 0; c0 < m; c0 += 4) {
+      const int mc = std::min(4, m - c0);
+      NYS_RETURN_IF(kmv_run(p, k, 1, prec, b.rows, b.cols, same,
+                            reinterpret_cast<const char *>(V) + c0 * eb, mc, ldv,
+                            reinterpret_cast<char *>(Out) + c0 * eb, ldo, alpha, beta, b.partial,
+                            b.vhi, b.vlo, s));
+    }
+    return NYS_OK;
+  }
+  const KmvPlan p = kmv_plan(b.rows.n, b.cols.n, m, prec, b.rows.Kp);
+  return kmv_run(p, k, deriv, prec, b.rows, b.cols, same, V, m, ldv, Out, ldo, alpha, beta,
+                 b.partial, b.vhi, b.vlo, s);
+}
+
+// ------------------------------------------------------------ kernel_matvec
+struct MatvecPlan {
+  KmvBufs kv;
+};
+void plan_matvec(MatvecPlan &p, int64_t nr, int64_t nc, int d, int m, int prec, Arena &ws) {
+  // the derivative product runs in chunks of <= 4 columns: reserve for both
+  plan_kmv(p.kv, nr, nc, d, std::min(m, 4), m, prec, ws);
+}
+
+// ------------------------------------------------------------ sketch
+struct SketchPlan {
+  double *G = nullptr, *Gpart = nullptr, *Linv = nullptr, *LinvT = nullptr, *Qtmp = nullptr;
+  int *flag = nullptr;
+  float *Q32 = nullptr, *Y32 = nullptr;
+  KmvBufs kv;
+};
+void plan_sketch(SketchPlan &p, int64_t n, int d, int r, int prec, Arena &ws) {
+  const int splits = gemm_tn_splits(n, r, r);
+  p.G = ws.take<double>((size_t)r * r);
+  p.Gpart = ws.take<double>((size_t)splits * r * r);
+  p.Linv = ws.take<double>((size_t)r * r);
+  p.LinvT = ws.take<double>((size_t)r * r);
+  p.Qtmp = ws.take<double>((size_t)n * r);
+  p.flag = ws.take<int>(4);
+  if (prec != NYS_FP64) {
+    p.Q32 = ws.take<float>((size_t)n * r);
+    p.Y32 = ws.take<float>((size_t)n * r);
+  }
+  plan_kmv(p.kv, n, n, d, r, r, prec, ws);
+}
+
+// ------------------------------------------------------------ precond build
+struct BuildPlan {
+  double *ssq_part = nullptr, *ssq = nullptr, *Ynu = nullptr, *Bm = nullptr;
+  double *M = nullptr, *Mpart = nullptr, *L = nullptr, *Linv = nullptr, *LinvT = nullptr;
+  double *G = nullptr, *Gs = nullptr, *Gbuf = nullptr, *Vev = nullptr, *w = nullptr, *T = nullptr;
+  double *jac = nullptr;
+  int *flag = nullptr, *rank = nullptr;
+};
+void plan_build(BuildPlan &p, int64_t n, int r, Arena &ws) {
+  const int64_t cnt = n * (int64_t)r;
+  const int splits = gemm_tn_splits(n, r, r);
+  p.ssq_part = ws.take<double>(sumsq_partial_elems(cnt));
+  p.ssq = ws.take<double>(1);
+  p.Ynu = ws.take<double>((size_t)cnt);
+  p.Bm = ws.take<double>((size_t)cnt);
+  p.M = ws.take<double>((size_t)r * r);
+  p.Mpart = ws.take<double>((size_t)splits * r * r);
+  p.L = ws.take<double>((size_t)r * r);
+  p.Linv = ws.take<double>((size_t)r * r);
+  p.LinvT = ws.take<double>((size_t)r * r);
+  p.G = ws.take<double>((size_t)r * r);
+  p.Gs = ws.take<double>((size_t)r * r);
+  p.Gbuf = ws.take<double>((size_t)r * r);
+  p.Vev = ws.take<double>((size_t)r * r);
+  p.w = ws.take<double>((size_t)r);
+  p.T = ws.take<double>((size_t)r * r);
+  p.jac = ws.take<double>(jacobi_scratch_elems(r));
+  p.flag = ws.take<int>(4);
+  p.rank = ws.take<int>(4);
+}
+
+// ------------------------------------------------------------ solve
+struct SolvePlan {
+  int prec = 0;
+  bool lowp = false, need64 = false;
+  KmvBufs kv;        // packed points in the solve precision
+  KmvBufs kv64;      // float64 packed points (refinement / true residual) when prec != FP64
+  char *X = nullptr, *R = nullptr, *Z = nullptr, *P = nullptr, *W = nullptr, *Spare = nullptr;
+  double *X64 = nullptr, *R64 = nullptr, *Spare64 = nullptr;
+  double *lam = nullptr, *rho = nullptr, *ab = nullptr, *rr = nullptr, *tmpc = nullptr;
+  double *red = nullptr;
+  int *bcol = nullptr, *restart = nullptr, *flag = nullptr, *idx = nullptr, *idx2 = nullptr;
+  char *pws = nullptr;
+  size_t pws_bytes = 0;
+};
+
+void plan_solve(SolvePlan &p, int64_t n, int d, int r, int m, int prec, bool refine, bool check_true,
+                Arena &ws) {
+  p.prec = prec;
+  p.lowp = prec != NYS_FP64;
+  p.need64 = p.lowp && (refine || check_true);
+  plan_kmv(p.kv, n, n, d, 1, m, prec, ws);
+  if (p.need64) plan_kmv(p.kv64, n, n, d, 1, m, NYS_FP64, ws);
+  const size_t vb = (size_t)n * m * elem_bytes(prec);
+  p.X = ws.take<char>(vb);
+  p.R = ws.take<char>(vb);
+  p.Z = ws.take<char>(vb);
+  p.P = ws.take<char>(vb);
+  p.W = ws.take<char>(vb);
+  p.Spare = ws.take<char>(vb);
+  if (p.lowp && (refine || check_true)) {
+    p.X64 = ws.take<double>((size_t)n * m);
+    p.R64 = ws.take<double>((size_t)n * m);
+    p.Spare64 = ws.take<double>((size_t)n * m);
+  } else if (check_true) {
+    p.R64 = ws.take<double>((size_t)n * m);
+  }
+  p.lam = ws.take<double>(m);
+  p.rho = ws.take<double>(m);
+  p.ab = ws.take<double>(m);
+  p.rr = ws.take<double>(m);
+  p.tmpc = ws.take<double>(m);
+  const ColRedShape sh = colred_shape(n, m);
+  p.red = ws.take<double>((size_t)sh.nb * m);
+  p.bcol = ws.take<int>(m);
+  p.restart = ws.take<int>(m);
+  p.flag = ws.take<int>(m);
+  p.idx = ws.take<int>(m);
+  p.idx2 = ws.take<int>(m);
+  if (r > 0) {
+    size_t mx = 0;
+    for (int mm = 1; mm <= m; ++mm) mx = std::max(mx, precond_apply_scratch_bytes(n, r, mm, prec));
+    p.pws_bytes = mx;
+    p.pws = ws.take<char>(mx);
+  }
+}
+
+struct DerivPlan {
+  KmvBufs kv;
+  double *tmp = nullptr, *red = nullptr, *out = nullptr;
+};
+void plan_deriv(DerivPlan &p, int64_t n, int d, Arena &ws) {
+  plan_kmv(p.kv, n, n, d, 1, 1, NYS_FP64, ws);
+  p.tmp = ws.take<double>((size_t)n);
+  p.red = ws.take<double>((size_t)colred_shape(n, 1).nb);
+  p.out = ws.take<double>(2);
+}
+
+template <class T>
+int32_t apply_precond_or_copy(const nys_precond *P, SolvePlan &sp, const T *R, int m, T *Z, int64_t n,
+                              hipStream_t s) {
+  if (!P) {
+    NYS_CHECK_HIP(hipMemcpyAsync(Z, R, sizeof(T) * n * m, hipMemcpyDeviceToDevice, s));
+    return NYS_OK;
+  }
+  Arena a;
+  a.base = sp.pws;
+  a.cap = sp.pws_bytes;
+  return precond_apply_impl<T>(*P, sp.lam, R, m, Z, a, s);
+}
+
+// The PCG driver.  Columns are kept compacted: slot s < ma holds original
+// column orig[s]; converged columns are written to Xsol and removed.
+template <class T>
+int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d, const double *B, int nrhs,
+                      const double *lambdas, int nlam, const nys_precond *P, const nys_pcg_opts &o,
+                      double *Xsol, nys_col_info *info, SolvePlan &sp, hipStream_t s) {
+  const int mtot = nlam * nrhs;
+  const int prec = sp.prec;
+  const bool lowp = sp.lowp;
+  const bool refine = lowp && o.refine_every >= 0;
+  const int max_refs = o.max_refinements > 0 ? o.max_refinements : 50;
+  T *X = reinterpret_cast<T *>(sp.X), *R = reinterpret_cast<T *>(sp.R), *Z = reinterpret_cast<T *>(sp.Z);
+  T *Pd = reinterpret_cast<T *>(sp.P), *W = reinterpret_cast<T *>(sp.W), *Sp = reinterpret_cast<T *>(sp.Spare);
+  double *X64 = sp.X64, *R64 = sp.R64, *Sp64 = sp.Spare64;
+
+  // points
+  NYS_RETURN_IF(prep_points(sp.kv, k, prec, Xpts, Xpts, d, s));
+  if (sp.need64) NYS_RETURN_IF(prep_points(sp.kv64, k, NYS_FP64, Xpts, Xpts, d, s));
+  KmvBufs &k64 = sp.need64 ? sp.kv64 : sp.kv;
+
+  // per-column setup
+  std::vector<int> orig(mtot), bcol_h(mtot);
+  std::vector<double> lam_h(mtot), bb(mtot);
+  for (int c = 0; c < mtot; ++c) {
+    orig[c] = c;
+    bcol_h[c] = c % nrhs;
+    lam_h[c] = lambdas[c / nrhs];
+    info[c] = nys_col_info{0, 0, NYS_NOT_CONVERGED, 0, 1.0, -1.0};
+  }
+  NYS_CHECK_HIP(hipMemcpyAsync(sp.bcol, bcol_h.data(), sizeof(int) * mtot, hipMemcpyHostToDevice, s));
+  NYS_CHECK_HIP(hipMemcpyAsync(sp.lam, lam_h.data(), sizeof(double) * mtot, hipMemcpyHostToDevice, s));
+  NYS_CHECK_HIP(hipMemsetAsync(sp.restart, 0, sizeof(int) * mtot, s));
+  NYS_CHECK_HIP(hipMemsetAsync(sp.flag, 0, sizeof(int) * mtot, s));
+  NYS_RETURN_IF(init_rhs<T>(B, nrhs, sp.bcol, R, X, n, mtot, s));
+  if (X64) NYS_RETURN_IF(launch_fill(X64, 0.0, n * (int64_t)mtot, s));
+  NYS_RETURN_IF(colred<T>(0, R, R, nullptr, nullptr, n, mtot, nullptr, sp.red, s));
+  NYS_RETURN_IF(colfinal(sp.red, n, mtot, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
+  NYS_CHECK_HIP(hipMemcpyAsync(bb.data(), sp.tmpc, sizeof(double) * mtot, hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < mtot; ++c)
+    if (!std::isfinite(bb[c])) {
+      set_error("nyspcg_solve: NaN or Inf in the right-hand side");
+      return NYS_ENUMERIC;
+    }
+
+  int ma = mtot;
+  std::vector<double> bb_s(bb);     // per slot
+  std::vector<double> rr_h(mtot), rt_h(mtot);
+  std::vector<int> flag_h(mtot), it_s(mtot, 0), ref_s(mtot, 0), restart_h(mtot, 0);
+  std::vector<int> keep, done, done_orig;
+  bool breakdown = false;
+
+  // compaction: keep slots listed in `keep`, in order
+  auto compact = [&](const std::vector<int> &kp) -> int32_t {
+    const int mn = (int)kp.size();
+    if (mn == ma) return NYS_OK;
+    if (mn > 0) {
+      NYS_CHECK_HIP(hipMemcpyAsync(sp.idx, kp.data(), sizeof(int) * mn, hipMemcpyHostToDevice, s));
+      NYS_RETURN_IF(gather_cols<T>(X, ma, sp.idx, mn, Sp, n, s));
+      std::swap(X, Sp);
+      NYS_RETURN_IF(gather_cols<T>(R, ma, sp.idx, mn, Sp, n, s));
+      std::swap(R, Sp);
+      NYS_RETURN_IF(gather_cols<T>(Pd, ma, sp.idx, mn, Sp, n, s));
+      std::swap(Pd, Sp);
+      if (X64) {
+        NYS_RETURN_IF(gather_cols<double>(X64, ma, sp.idx, mn, Sp64, n, s));
+        std::swap(X64, Sp64);
+      }
+      NYS_RETURN_IF(gather_cols<double>(sp.rho, ma, sp.idx, mn, sp.tmpc, 1, s));
+      NYS_CHECK_HIP(hipMemcpyAsync(sp.rho, sp.tmpc, sizeof(double) * mn, hipMemcpyDeviceToDevice, s));
+    }
+    std::vector<int> o2(mn), b2(mn);
+    std::vector<double> l2(mn), bb2(mn);
+    std::vector<int> it2(mn), rf2(mn);
+    for (int q = 0; q < mn; ++q) {
+      o2[q] = orig[kp[q]];
+      b2[q] = bcol_h[kp[q]];
+      l2[q] = lam_h[kp[q]];
+      bb2[q] = bb_s[kp[q]];
+      it2[q] = it_s[kp[q]];
+      rf2[q] = ref_s[kp[q]];
+    }
+    orig = o2;
+    bcol_h = b2;
+    lam_h = l2;
+    bb_s = bb2;
+    it_s = it2;
+    ref_s = rf2;
+    ma = mn;
+    if (mn > 0) {
+      NYS_CHECK_HIP(hipMemcpyAsync(sp.bcol, bcol_h.data(), sizeof(int) * mn, hipMemcpyHostToDevice, s));
+      NYS_CHECK_HIP(hipMemcpyAsync(sp.lam, lam_h.data(), sizeof(double) * mn, hipMemcpyHostToDevice, s));
+    }
+    NYS_CHECK_HIP(hipStreamSynchronize(s));  // host index vectors may go out of scope
+    return NYS_OK;
+  };
+  // write finished slots to Xsol
+  auto finish = [&](const std::vector<int> &slots) -> int32_t {
+    if (slots.empty()) return NYS_OK;
+    std::vector<int> og(slots.size());
+    for (size_t q = 0; q < slots.size(); ++q) og[q] = orig[slots[q]];
+    NYS_CHECK_HIP(hipMemcpyAsync(sp.idx, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, s));
+    NYS_CHECK_HIP(hipMemcpyAsync(sp.idx2, og.data(), sizeof(int) * og.size(), hipMemcpyHostToDevice, s));
+    NYS_RETURN_IF(scatter_sol<T>(X, X64, ma, sp.idx, sp.idx2, (int)slots.size(), Xsol, mtot, n, s));
+    // make the host vectors safe to reuse before the copies complete
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    return NYS_OK;
+  };
+
+  // zero right-hand sides: x = 0 after 0 iterations
+  {
+    std::vector<int> z, kp;
+    for (int c = 0; c < ma; ++c) (bb_s[c] == 0.0 ? z : kp).push_back(c);
+    for (int c : z) {
+      info[orig[c]].status = NYS_OK;
+      info[orig[c]].relres_recursive = 0.0;
+      info[orig[c]].relres_true = 0.0;
+    }
+    NYS_RETURN_IF(finish(z));
+    NYS_RETURN_IF(compact(kp));
+  }
+  if (ma > 0 && o.max_iters > 0) {
+    NYS_RETURN_IF(apply_precond_or_copy<T>(P, sp, R, ma, Z, n, s));
+    NYS_RETURN_IF(colred<T>(0, R, Z, nullptr, nullptr, n, ma, nullptr, sp.red, s));
+    NYS_RETURN_IF(colfinal(sp.red, n, ma, 0, sp.rho, nullptr, nullptr, nullptr, nullptr, s));
+    NYS_CHECK_HIP(hipMemcpyAsync(Pd, Z, sizeof(T) * n * ma, hipMemcpyDeviceToDevice, s));
+  }
+  const double tol = o.tol;
+  int iter = 0;
+  while (ma > 0) {
+    if (iter >= o.max_iters) break;
+    ++iter;
+    // w = K p + lambda p ; alpha = rho / p^T w
+    NYS_RETURN_IF(run_kmv(sp.kv, k, 0, prec, 1, Pd, ma, ma, W, ma, 1.0, 0.0, s));
+    NYS_RETURN_IF(colred<T>(1, Pd, W, nullptr, nullptr, n, ma, sp.lam, sp.red, s));
+    NYS_RETURN_IF(colfinal(sp.red, n, ma, 1, nullptr, sp.rho, sp.ab, nullptr, sp.flag, s));
+    // x += alpha p ; r -= alpha w ; rr = r^T r
+    NYS_RETURN_IF(colred<T>(2, Pd, W, X, R, n, ma, sp.ab, sp.red, s));
+    NYS_RETURN_IF(colfinal(sp.red, n, ma, 0, sp.rr, nullptr, nullptr, nullptr, nullptr, s));
+    NYS_CHECK_HIP(hipMemcpyAsync(rr_h.data(), sp.rr, sizeof(double) * ma, hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipMemcpyAsync(flag_h.data(), sp.flag, sizeof(int) * ma, hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+
+    std::vector<char> conv(ma, 0), stop(ma, 0);
+    bool any_conv = false, any_restart = false;
+    for (int q = 0; q < ma; ++q) {
+      it_s[q] += 1;
+      const double rel = std::sqrt(std::max(rr_h[q], 0.0) / bb_s[q]);
+      info[orig[q]].iters = it_s[q];
+      info[orig[q]].relres_recursive = rel;
+      if (flag_h[q] || !std::isfinite(rel)) {
+        stop[q] = 1;
+        breakdown = true;
+        info[orig[q]].status = NYS_ENOTPD;
+        continue;
+      }
+      if (rel <= tol) {
+        conv[q] = 1;
+        any_conv = true;
+      }
+    }
+    const bool periodic = refine && o.refine_every > 0 && (iter % o.refine_every == 0);
+    if (refine && (any_conv || periodic)) {
+      // float64 residual replacement: x64 += x, r = b - (K + lambda I) x64
+      NYS_RETURN_IF(flush_x(reinterpret_cast<float *>(X), X64, n * (int64_t)ma, s));
+      NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, X64, ma, ma, R64, ma, 1.0, 0.0, s));
+      NYS_RETURN_IF(residual64(B, nrhs, sp.bcol, sp.lam, X64, R64, reinterpret_cast<float *>(R), n, ma, s));
+      NYS_RETURN_IF(colred<double>(0, R64, R64, nullptr, nullptr, n, ma, nullptr, sp.red, s));
+      NYS_RETURN_IF(colfinal(sp.red, n, ma, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
+      NYS_CHECK_HIP(hipMemcpyAsync(rt_h.data(), sp.tmpc, sizeof(double) * ma, hipMemcpyDeviceToHost, s));
+      NYS_CHECK_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < ma; ++q) {
+        if (stop[q]) continue;
+        ref_s[q] += 1;
+        const double rel = std::sqrt(std::max(rt_h[q], 0.0) / bb_s[q]);
+        info[orig[q]].refinements = ref_s[q];
+        info[orig[q]].relres_true = rel;
+        conv[q] = rel <= tol;
+        restart_h[q] = (o.refine_mode == 1) ? 1 : 0;
+        if (restart_h[q]) any_restart = true;
+        if (!conv[q] && ref_s[q] >= max_refs) stop[q] = 1;
+      }
+    }
+    // collect finished columns
+    std::vector<int> fin, kp;
+    for (int q = 0; q < ma; ++q) {
+      const bool over = it_s[q] >= o.max_iters;
+      if (conv[q]) info[orig[q]].status = NYS_OK;
+      if (conv[q] || stop[q] || over) fin.push_back(q);
+      else kp.push_back(q);
+    }
+    if (!fin.empty()) {
+      NYS_RETURN_IF(finish(fin));
+      std::vector<int> rs(kp.size());
+      for (size_t q = 0; q < kp.size(); ++q) rs[q] = restart_h[kp[q]];
+      NYS_RETURN_IF(compact(kp));
+      restart_h.assign(mtot, 0);
+      for (size_t q = 0; q < rs.size(); ++q) restart_h[q] = rs[q];
+      any_restart = false;
+      for (int q = 0; q < ma; ++q) any_restart |= restart_h[q] != 0;
+      NYS_CHECK_HIP(hipMemsetAsync(sp.flag, 0, sizeof(int) * std::max(ma, 1), s));
+    }
+    if (ma == 0) break;
+    if (any_restart) {
+      NYS_CHECK_HIP(hipMemcpyAsync(sp.restart, restart_h.data(), sizeof(int) * ma, hipMemcpyHostToDevice, s));
+      NYS_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    // z = P^{-1} r ; beta = r^T z / rho ; p = z + beta p
+    NYS_RETURN_IF(apply_precond_or_copy<T>(P, sp, R, ma, Z, n, s));
+    NYS_RETURN_IF(colred<T>(0, R, Z, nullptr, nullptr, n, ma, nullptr, sp.red, s));
+    NYS_RETURN_IF(colfinal(sp.red, n, ma, 2, nullptr, sp.rho, sp.ab, any_restart ? sp.restart : nullptr,
+                           nullptr, s));
+    NYS_RETURN_IF(p_update<T>(Pd, Z, sp.ab, n, ma, s));
+    if (any_restart) {
+      NYS_CHECK_HIP(hipMemsetAsync(sp.restart, 0, sizeof(int) * ma, s));
+      std::fill(restart_h.begin(), restart_h.end(), 0);
+    }
+  }
+  // columns still active hit the iteration cap
+  if (ma > 0) {
+    std::vector<int> all(ma);
+    for (int q = 0; q < ma; ++q) all[q] = q;
+    if (refine) {
+      NYS_RETURN_IF(flush_x(reinterpret_cast<float *>(X), X64, n * (int64_t)ma, s));
+      NYS_CHECK_HIP(hipMemsetAsync(X, 0, sizeof(T) * n * ma, s));
+    }
+    NYS_RETURN_IF(finish(all));
+  }
+  // optional float64 true residual of every column
+  if (o.check_true && R64) {
+    NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, Xsol, mtot, mtot, R64, mtot, 1.0, 0.0, s));
+    std::vector<int> bc(mtot);
+    std::vector<double> lm(mtot);
+    for (int c = 0; c < mtot; ++c) {
+      bc[c] = c % nrhs;
+      lm[c] = lambdas[c / nrhs];
+    }
+    NYS_CHECK_HIP(hipMemcpyAsync(sp.bcol, bc.data(), sizeof(int) * mtot, hipMemcpyHostToDevice, s));
+    NYS_CHECK_HIP(hipMemcpyAsync(sp.lam, lm.data(), sizeof(double) * mtot, hipMemcpyHostToDevice, s));
+    NYS_RETURN_IF(residual64(B, nrhs, sp.bcol, sp.lam, Xsol, R64, nullptr, n, mtot, s));
+    NYS_RETURN_IF(colred<double>(0, R64, R64, nullptr, nullptr, n, mtot, nullptr, sp.red, s));
+    NYS_RETURN_IF(colfinal(sp.red, n, mtot, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
+    std::vector<double> rt(mtot);
+    NYS_CHECK_HIP(hipMemcpyAsync(rt.data(), sp.tmpc, sizeof(double) * mtot, hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < mtot; ++c)
+      info[c].relres_true = bb[c] > 0 ? std::sqrt(std::max(rt[c], 0.0) / bb[c]) : 0.0;
+  }
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (breakdown) {
+    set_error("nyspcg_solve: PCG breakdown (p^T A p <= 0 or non-finite) in at least one column");
+    return NYS_ENOTPD;
+  }
+  for (int c = 0; c < mtot; ++c)
+    if (info[c].status != NYS_OK) return NYS_NOT_CONVERGED;
+  return NYS_OK;
+}
+
+int32_t check_precond(const nys_precond *P, int64_t n, int prec) {
+  if (!P) return NYS_OK;
+  if (P->n != n) return einval("preconditioner built for a different n");
+  if (P->r < 1 || !P->U || !P->lam_hat) return einval("preconditioner buffers missing");
+  if (prec != NYS_FP64 && !P->U32) return einval("FP32/BF16X3 solves need the float32 copy U32");
+  return NYS_OK;
+}
+
+int32_t check_opts(const nys_pcg_opts *o) {
+  if (!o) return einval("opts is NULL");
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return einval("tol must be positive");
+  if (o->max_iters < 0) return einval("max_iters must be >= 0");
+  if (!valid_prec(o->prec)) return einval("unsupported precision");
+  if (o->refine_mode != 0 && o->refine_mode != 1) return einval("refine_mode must be 0 or 1");
+  return NYS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *nys_last_error(void) { return last_error_cstr(); }
+const char *nys_version(void) { return "libnys 0.1.0 (gfx950)"; }
+
+int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_t r, int32_t m,
+                            int32_t prec, size_t *bytes) {
+  if (!bytes) return einval("bytes is NULL");
+  if (n < 0 || n2 < 0 || d < 0 || r < 0 || m < 0) return einval("negative size");
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  Arena a;
+  switch (op) {
+    case NYS_OP_KERNEL_MATVEC: {
+      MatvecPlan p;
+      plan_matvec(p, std::max<int64_t>(n, 1), std::max<int64_t>(n2, 1), std::max(d, 1), std::max(m, 1), prec, a);
+      break;
+    }
+    case NYS_OP_SKETCH: {
+      SketchPlan p;
+      plan_sketch(p, std::max<int64_t>(n, 1), std::max(d, 1), std::max(r, 1), prec, a);
+      break;
+    }
+    case NYS_OP_PRECOND_BUILD: {
+      BuildPlan p;
+      plan_build(p, std::max<int64_t>(n, 1), std::max(r, 1), a);
+      break;
+    }
+    case NYS_OP_PRECOND_APPLY:
+      a.off = precond_apply_scratch_bytes(std::max<int64_t>(n, 1), std::max(r, 1), std::max(m, 1), prec);
+      break;
+    case NYS_OP_SOLVE: {
+      SolvePlan p;
+      plan_solve(p, std::max<int64_t>(n, 1), std::max(d, 1), r, std::max(m, 1), prec, true, true, a);
+      break;
+    }
+    case NYS_OP_BACKWARD: {
+      SolvePlan p;
+      plan_solve(p, std::max<int64_t>(n, 1), std::max(d, 1), r, 1, prec, true, true, a);
+      DerivPlan q;
+      plan_deriv(q, std::max<int64_t>(n, 1), std::max(d, 1), a);
+      break;
+    }
+    default:
+      return einval("unknown op");
+  }
+  *bytes = a.off;
+  return NYS_OK;
+}
+
+int32_t kernel_matvec(nys_kernel k, int32_t deriv, int32_t prec, const double *Xr, int64_t nr,
+                      const double *Xc, int64_t nc, int32_t d, const void *V, int32_t m, void *Out,
+                      double alpha, double beta, void *ws, size_t ws_bytes, void *stream) {
+  NYS_RETURN_IF(check_kernel(k));
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (deriv != 0 && deriv != 1) return einval("deriv must be 0 or 1");
+  if (nr < 0 || nc < 0 || m < 0) return einval("negative size");
+  if (d < 1 || d > max_dim(prec)) return einval("d out of range for this precision");
+  if (nr == 0 || m == 0) return NYS_OK;
+  if (nc == 0) return einval("nc must be >= 1");
+  if (!Xr || !Xc || !V || !Out) return einval("null pointer");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return einval("alpha/beta must be finite");
+  if (!ws) return einval("ws is NULL");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  MatvecPlan p;
+  plan_matvec(p, nr, nc, d, m, prec, a);
+  NYS_RETURN_IF(check_ws(a));
+  const int same = (Xr == Xc && nr == nc) ? 1 : 0;
+  NYS_RETURN_IF(prep_points(p.kv, k, prec, Xr, Xc, d, s));
+  return run_kmv(p.kv, k, deriv, prec, same, V, m, m, Out, m, alpha, beta, s);
+}
+
+int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32_t d, double *Omega,
+                   int32_t r, double *Y, void *ws, size_t ws_bytes, void *stream) {
+  NYS_RETURN_IF(check_kernel(k));
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (n < 1 || d < 1 || d > max_dim(prec)) return einval("n >= 1 and 1 <= d <= max required");
+  if (r < 1 || r > n || r > 1024) return einval("need 1 <= r <= min(n, 1024)");
+  if (!X || !Omega || !Y || !ws) return einval("null pointer");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  SketchPlan p;
+  plan_sketch(p, n, d, r, prec, a);
+  NYS_RETURN_IF(check_ws(a));
+  // Q = Omega L^{-T} with L L^T = Omega^T Omega (Cholesky QR)
+  const int splits = gemm_tn_splits(n, r, r);
+  NYS_RETURN_IF(gemm_tn<double>(Omega, r, Omega, r, n, r, r, p.G, r, p.Gpart, splits, s));
+  NYS_RETURN_IF(launch_chol(p.G, r, p.flag, s));
+  int flag = 0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    set_error("nys_sketch: the test matrix Omega is rank deficient or not finite");
+    return NYS_ENOTPD;
+  }
+  NYS_RETURN_IF(launch_trinv_lower(p.G, p.Linv, r, s));
+  NYS_RETURN_IF(launch_transpose(p.Linv, p.LinvT, r, s));
+  NYS_RETURN_IF(gemm_nn<double>(Omega, r, p.LinvT, r, n, r, r, p.Qtmp, r, 0, nullptr, 0, nullptr, s));
+  NYS_CHECK_HIP(hipMemcpyAsync(Omega, p.Qtmp, sizeof(double) * n * r, hipMemcpyDeviceToDevice, s));
+  // Y = K Q
+  NYS_RETURN_IF(prep_points(p.kv, k, prec, X, X, d, s));
+  if (prec == NYS_FP64) {
+    NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, Omega, r, r, Y, r, 1.0, 0.0, s));
+  } else {
+    NYS_RETURN_IF(launch_copy_d2f(Omega, p.Q32, n * (int64_t)r, s));
+    NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, p.Q32, r, r, p.Y32, r, 1.0, 0.0, s));
+    NYS_RETURN_IF(launch_copy_f2d(p.Y32, Y, n * (int64_t)r, s));
+  }
+  return NYS_OK;
+}
+
+int32_t nys_precond_build(const double *Y, const double *Q, int64_t n, int32_t r, int32_t sketch_prec,
+                          nys_precond *P, void *ws, size_t ws_bytes, void *stream) {
+  if (!Y || !Q || !P || !ws) return einval("null pointer");
+  if (!valid_prec(sketch_prec)) return einval("unsupported precision");
+  if (n < 1 || r < 1 || r > n || r > 1024) return einval("need 1 <= r <= min(n, 1024)");
+  if (P->n != n || P->r != r || !P->U || !P->lam_hat) return einval("preconditioner buffers do not match n, r");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  BuildPlan p;
+  plan_build(p, n, r, a);
+  NYS_RETURN_IF(check_ws(a));
+  const int64_t cnt = n * (int64_t)r;
+  NYS_RETURN_IF(launch_sumsq(Y, cnt, p.ssq_part, p.ssq, s));
+  double ssq = 0.0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&ssq, p.ssq, sizeof(double), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(ssq)) {
+    set_error("nys_precond_build: NaN or Inf in the sketch");
+    return NYS_ENUMERIC;
+  }
+  const double yf = std::sqrt(ssq);
+  const double cprec = sketch_prec == NYS_FP64 ? 0.0 : (sketch_prec == NYS_FP32 ? std::ldexp(1.0, -21) : std::ldexp(1.0, -14));
+  double nu = std::max(std::sqrt((double)n) * std::ldexp(1.0, -52) * yf, cprec * yf / std::sqrt((double)r));
+  if (!(nu > 0.0)) nu = std::ldexp(1.0, -52);
+  const int splits = gemm_tn_splits(n, r, r);
+  bool ok = false;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    NYS_CHECK_HIP(hipMemcpyAsync(p.Ynu, Y, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+    NYS_RETURN_IF(launch_axpy(nu, Q, p.Ynu, cnt, s));
+    NYS_RETURN_IF(gemm_tn<double>(Q, r, p.Ynu, r, n, r, r, p.M, r, p.Mpart, splits, s));
+    NYS_RETURN_IF(launch_symmetrise(p.M, p.L, r, s));
+    NYS_RETURN_IF(launch_chol(p.L, r, p.flag, s));
+    int flag = 0;
+    NYS_CHECK_HIP(hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    if (flag == 0) {
+      ok = true;
+      break;
+    }
+    nu *= 10.0;
+  }
+  if (!ok) {
+    set_error("nys_precond_build: shifted Cholesky of the sketch core failed after 5 retries");
+    return NYS_ENOTPD;
+  }
+  // B = Y_nu L^{-T};  B^T B = V S^2 V^T;  U = B V S^{-1}
+  NYS_RETURN_IF(launch_trinv_lower(p.L, p.Linv, r, s));
+  NYS_RETURN_IF(launch_transpose(p.Linv, p.LinvT, r, s));
+  NYS_RETURN_IF(gemm_nn<double>(p.Ynu, r, p.LinvT, r, n, r, r, p.Bm, r, 0, nullptr, 0, nullptr, s));
+  NYS_RETURN_IF(gemm_tn<double>(p.Bm, r, p.Bm, r, n, r, r, p.G, r, p.Mpart, splits, s));
+  NYS_RETURN_IF(launch_symmetrise(p.G, p.Gs, r, s));
+  NYS_RETURN_IF(jacobi_eig(p.Gs, p.Gbuf, p.Vev, p.w, r, p.jac, s));
+  NYS_RETURN_IF(launch_eig_finish(p.w, p.Vev, r, nu, p.T, P->lam_hat, p.rank, s));
+  NYS_RETURN_IF(gemm_nn<double>(p.Bm, r, p.T, r, n, r, r, P->U, r, 0, nullptr, 0, nullptr, s));
+  if (P->U32) NYS_RETURN_IF(launch_copy_d2f(P->U, P->U32, cnt, s));
+  int rank = 0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&rank, p.rank, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  P->rank = rank;
+  P->nu = nu;
+  return NYS_OK;
+}
+
+int32_t nys_precond_apply(const nys_precond *P, const double *lambdas, int32_t prec, const void *R,
+                          int32_t m, void *Z, void *ws, size_t ws_bytes, void *stream) {
+  if (!P || !lambdas || !R || !Z || !ws) return einval("null pointer");
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (m < 1) return einval("m must be >= 1");
+  NYS_RETURN_IF(check_precond(P, P->n, prec));
+  if (R == Z) return einval("R and Z must not overlap");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  if (a.cap < precond_apply_scratch_bytes(P->n, P->r, m, prec)) {
+    set_error("workspace smaller than nys_workspace_bytes() for these arguments");
+    return NYS_ENOMEM;
+  }
+  if (prec == NYS_FP64)
+    return precond_apply_impl<double>(*P, lambdas, reinterpret_cast<const double *>(R), m,
+                                      reinterpret_cast<double *>(Z), a, s);
+  return precond_apply_impl<float>(*P, lambdas, reinterpret_cast<const float *>(R), m,
+                                   reinterpret_cast<float *>(Z), a, s);
+}
+
+int32_t nyspcg_solve(nys_kernel k, const double *X, int64_t n, int32_t d, const double *B, int32_t nrhs,
+                     const double *lambdas, int32_t nlam, const nys_precond *P, const nys_pcg_opts *opts,
+                     double *Xsol, nys_col_info *info, void *ws, size_t ws_bytes, void *stream) {
+  NYS_RETURN_IF(check_kernel(k));
+  NYS_RETURN_IF(check_opts(opts));
+  const int prec = opts->prec;
+  if (n < 1 || d < 1 || d > max_dim(prec)) return einval("n >= 1 and 1 <= d <= max required");
+  if (nrhs < 1 || nlam < 1) return einval("nrhs and nlam must be >= 1");
+  if ((int64_t)nrhs * nlam > 4096) return einval("at most 4096 columns per solve");
+  if (!X || !B || !lambdas || !Xsol || !info || !ws) return einval("null pointer");
+  for (int l = 0; l < nlam; ++l)
+    if (!(lambdas[l] > 0.0) || !std::isfinite(lambdas[l])) return einval("every lambda must be > 0 and finite");
+  NYS_RETURN_IF(check_precond(P, n, prec));
+  hipStream_t s = as_stream(stream);
+  const int m = nrhs * nlam;
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  SolvePlan sp;
+  plan_solve(sp, n, d, P ? P->r : 0, m, prec, opts->refine_every >= 0, opts->check_true != 0, a);
+  NYS_RETURN_IF(check_ws(a));
+  if (prec == NYS_FP64)
+    return solve_columns<double>(k, X, n, d, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, s);
+  return solve_columns<float>(k, X, n, d, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, s);
+}
+
+int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, double lambda,
+                        const double *xsol, const double *gx, const nys_precond *P, const nys_pcg_opts *opts,
+                        double *adj, double *dL_dlambda, double *dL_dsigma, nys_col_info *info, void *ws,
+                        size_t ws_bytes, void *stream) {
+  NYS_RETURN_IF(check_kernel(k));
+  NYS_RETURN_IF(check_opts(opts));
+  const int prec = opts->prec;
+  if (n < 1 || d < 1 || d > max_dim(NYS_FP64)) return einval("n >= 1 and 1 <= d <= 62 required");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return einval("lambda must be > 0");
+  if (!X || !xsol || !gx || !adj || !dL_dlambda || !dL_dsigma || !info || !ws) return einval("null pointer");
+  NYS_RETURN_IF(check_precond(P, n, prec));
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  SolvePlan sp;
+  plan_solve(sp, n, d, P ? P->r : 0, 1, prec, opts->refine_every >= 0, opts->check_true != 0, a);
+  DerivPlan dp;
+  plan_deriv(dp, n, d, a);
+  NYS_RETURN_IF(check_ws(a));
+  // adjoint solve (K + lambda I) a = gx with the same preconditioner
+  int32_t rc;
+  if (prec == NYS_FP64)
+    rc = solve_columns<double>(k, X, n, d, gx, 1, &lambda, 1, P, *opts, adj, info, sp, s);
+  else
+    rc = solve_columns<float>(k, X, n, d, gx, 1, &lambda, 1, P, *opts, adj, info, sp, s);
+  if (rc < 0) return rc;
+  // dL/dlambda = -a^T x ;  dL/dsigma = -a^T (dK/dsigma) x
+  NYS_RETURN_IF(prep_points(dp.kv, k, NYS_FP64, X, X, d, s));
+  NYS_RETURN_IF(run_kmv(dp.kv, k, 1, NYS_FP64, 1, xsol, 1, 1, dp.tmp, 1, 1.0, 0.0, s));
+  NYS_RETURN_IF(colred<double>(0, adj, const_cast<double *>(xsol), nullptr, nullptr, n, 1, nullptr, dp.red, s));
+  NYS_RETURN_IF(colfinal(dp.red, n, 1, 0, dp.out, nullptr, nullptr, nullptr, nullptr, s));
+  NYS_RETURN_IF(colred<double>(0, adj, dp.tmp, nullptr, nullptr, n, 1, nullptr, dp.red, s));
+  NYS_RETURN_IF(colfinal(dp.red, n, 1, 0, dp.out + 1, nullptr, nullptr, nullptr, nullptr, s));
+  double h[2] = {0, 0};
+  NYS_CHECK_HIP(hipMemcpyAsync(h, dp.out, sizeof(h), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  *dL_dlambda = -h[0];
+  *dL_dsigma = -h[1];
+  return rc;
+}
+
+}  // extern "C"

