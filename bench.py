@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark of the NysPCG hot path on one MI355X.
+
+Workload (default): the batched lambda-grid problem at n = 1e6 points, d = 16,
+RBF kernel sigma = 4, 64 right-hand sides b_c = sign(X w_c) times 8 lambdas
+log-spaced over [1e-7 n, 1e-3 n] (512 independent columns), one shared Nystrom
+sketch of rank 500, BF16X3 kernel products, float32 CG with float64 residual
+refinement, tolerance 1e-6 on the float64 true relative residual.
+
+One step = sketch + preconditioner build + PCG to tolerance for every column
+(the paper counts the preconditioner build in the solve time, section "Large-Scale
+Ridge Regression with NysPCG").  Data generation, device placement and the
+Gaussian test matrix are outside the timer; one warmup capped at 10 iterations
+precedes the timed steps (section "Hardware, Timing, and Solver Settings").
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NysPCG time-to-1e-6 rel. residual + kernel_matvec TFLOP/s, n=1e6 d=16"
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense bf16 MFMA
+HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--refine-every", type=int, default=0)
+    ap.add_argument("--refine-mode", type=int, default=1)
+    ap.add_argument("--kmv-reps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kmv-only", action="store_true", help="time the kernel product only (profiling)")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if args.verbose:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def time_kernel_matvec(nys, torch, X, sigma, m, prec, reps):
+    """Average duration of one kernel_matvec call (HIP events on the stream it runs on)."""
+    g = torch.Generator(device=X.device)
+    g.manual_seed(1234)
+    V = torch.randn((X.shape[0], m), generator=g, device=X.device, dtype=torch.float32)
+    out = torch.empty_like(V)
+    nys.kernel_matvec(X, X, V, nys.RBF, sigma, prec, out=out)     # untimed first call
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        nys.kernel_matvec(X, X, V, nys.RBF, sigma, prec, out=out)
+    e.record()
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / 1e3 / reps
+    del V, out
+    return t
+
+
+def cpu_baseline(args, w, gpu_info):
+    """The oracle's K V (float64 NumPy) on a bounded row sample of the same workload,
+    scaled to a full time-to-solution estimate with the GPU run's product count."""
+    import numpy as np
+    import oracle as o
+
+    n, m = w.n, 512
+    rng = np.random.default_rng(7)
+    V = rng.standard_normal((n, m))
+    cores = os.cpu_count() or 1
+    rows = 8
+    t0 = time.perf_counter()
+    o.kernel_matvec_rows(w.X[:rows], w.X, V, w.kind, w.sigma)
+    t_small = time.perf_counter() - t0
+    rows = max(rows, min(n, int(rows * args.cpu_seconds / max(t_small, 1e-3))))
+    t0 = time.perf_counter()
+    o.kernel_matvec_rows(w.X[:rows], w.X, V, w.kind, w.sigma)
+    t_rows = time.perf_counter() - t0
+    t_kv = t_rows * n / rows                       # one full 512-column K V, extrapolated
+    kv_equiv = gpu_info["kv_equivalents"]
+    est = t_kv * kv_equiv
+    return {
+        "value": est, "unit": "s", "cores": cores, "kind": "oracle",
+        "sample": (f"oracle float64 K(X[0:{rows}], X) V with V n x 512 on the n={n} point set took "
+                   f"{t_rows:.1f} s ({cores} host threads, {cpu_model()}); extrapolated x{n / rows:.0f} "
+                   f"to one full 512-column product ({t_kv:.0f} s) and x{kv_equiv:.1f} to the GPU run's "
+                   f"products (sum of column iterations and float64 refinements / 512)"),
+        "kernel_matvec_tflops": n * n * (2 * w.d + 2 * m) / t_kv / 1e12,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import nys_inputs as ni
+    import paper_2609_08136_amd as nys
+
+    nys.load()
+    dev = torch.device("cuda:0")
+    w = ni.batched_lambda_grid(args.seed, n=args.n)
+    n, d, r = w.n, w.d, w.r
+    nrhs, nlam = w.B.shape[1], len(w.lambdas)
+    m = nrhs * nlam
+    # the smallest lambda (1e-7 n) lies below the three-term distance error, so the
+    # six-term distance split is needed for a positive-definite perturbed operator
+    prec = nys.BF16X3_D6
+    X = torch.from_numpy(w.X).to(dev)
+    B = torch.from_numpy(w.B).to(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed + ni.OMEGA_SEED_OFFSET)
+    Omega0 = torch.randn((n, r), generator=g, device=dev, dtype=torch.float64)
+    Om = torch.empty_like(Omega0)
+    log(args, f"inputs ready: n={n} d={d} r={r} columns={m}")
+
+    # ---- dominant kernel: the 512-column BF16X3 product (the solve's first product width)
+    t_kmv = time_kernel_matvec(nys, torch, X, w.sigma, m, prec, args.kmv_reps)
+    flops = n * n * (2 * d + 2 * m)
+    kmv_tflops = flops / t_kmv / 1e12
+    log(args, f"kernel_matvec m={m}: {t_kmv * 1e3:.1f} ms, {kmv_tflops:.1f} TFLOP/s")
+    t_kmv1 = time_kernel_matvec(nys, torch, X, w.sigma, 1, prec, args.kmv_reps)
+    log(args, f"kernel_matvec m=1: {t_kmv1 * 1e3:.1f} ms")
+    if args.kmv_only:
+        print(json.dumps({"kernel_matvec_ms": t_kmv * 1e3, "tflops": kmv_tflops, "m1_ms": t_kmv1 * 1e3}))
+        return
+
+    ws = torch.empty(nys.nys_workspace_bytes(nys.OP_SOLVE, n, 0, d, r, m, prec), dtype=torch.uint8, device=dev)
+
+    def step(max_iters):
+        Om.copy_(Omega0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Y = nys.nys_sketch(X, Om, w.kind, w.sigma, prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P = nys.nys_precond_build(Y, Om, prec, with_fp32=True)
+        del Y
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        Xs, info, rc = nys.nyspcg_solve(X, B, w.lambdas, w.kind, w.sigma, P, tol=w.tol, max_iters=max_iters,
+                                        prec=prec, refine_every=args.refine_every, refine_mode=args.refine_mode,
+                                        workspace=ws)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return Xs, info, rc, P, (t1 - t0, t2 - t1, t3 - t2, t3 - t0)
+
+    for _ in range(args.warmup):
+        step(10)
+        log(args, "warmup done")
+    times, phases, last = [], [], None
+    for _ in range(args.steps):
+        Xs, info, rc, P, ph = step(1000)
+        times.append(ph[3])
+        phases.append(ph)
+        last = (Xs, info, rc, P)
+        log(args, f"step: sketch {ph[0]:.2f}s build {ph[1]:.2f}s solve {ph[2]:.2f}s total {ph[3]:.2f}s rc={rc}")
+    Xs, info, rc, P = last
+    t_step = statistics.median(times)
+
+    # ---- acceptance, after the timer: every column's float64 true relative residual
+    rel_true = [c["relres_true"] for c in info]
+    ok = all(0 <= v <= w.tol for v in rel_true) and rc == nys.OK
+    iters = [c["iters"] for c in info]
+    refs = [c["refinements"] for c in info]
+    # independent check on sampled rows: r_i = b_i - (K x)_i - lambda x_i in float64
+    rows = torch.from_numpy(np.sort(np.random.default_rng(3).choice(n, 256, replace=False))).to(dev)
+    KX = nys.kernel_matvec(X[rows].contiguous(), X, Xs, w.kind, w.sigma, nys.FP64)
+    lam_col = torch.tensor([w.lambdas[c // nrhs] for c in range(m)], dtype=torch.float64, device=dev)
+    Bcol = B[:, [c % nrhs for c in range(m)]]
+    res = Bcol[rows] - KX - lam_col * Xs[rows]
+    sampled = (res.norm(dim=0) / Bcol[rows].norm(dim=0)).max().item()
+    per_lambda = {f"{w.lambdas[l]:.3g}": max(iters[l * nrhs:(l + 1) * nrhs]) for l in range(nlam)}
+    kv_equiv = (sum(iters) + sum(refs) * 5) / m   # a float64 column product costs ~5 BF16X3 ones
+    gpu_info = {"kv_equivalents": kv_equiv}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, w, gpu_info)
+
+    out = {
+        "metric": METRIC,
+        "value": round(t_step, 3),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 1),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched_lambda_grid",
+            "n": n, "d": d, "kernel": "rbf", "sigma": w.sigma, "nrhs": nrhs, "nlam": nlam,
+            "lambdas": [float(v) for v in w.lambdas], "rank": r, "tol": w.tol,
+            "precision": "bf16x3 K V, fp32 CG, fp64 residual refinement",
+            "refine_every": args.refine_every, "refine_mode": args.refine_mode,
+        },
+        "kernel_matvec_tflops": round(kmv_tflops, 1),
+        "kernel_matvec": {"m": m, "ms": round(t_kmv * 1e3, 2), "tflops": round(kmv_tflops, 1),
+                          "m1_ms": round(t_kmv1 * 1e3, 2),
+                          "m1_gpairs_per_s": round(n * n / t_kmv1 / 1e9, 1)},
+        "roofline": {
+            "bound": "mfma",
+            "achieved": round(kmv_tflops, 1),
+            "peak": round(PEAK_BF16_TFLOPS / 3.0, 1),
+            "unit": "TFLOP/s",
+            "frac": round(kmv_tflops / (PEAK_BF16_TFLOPS / 3.0), 4),
+            "traffic": None,
+        },
+        "phases_s": {"sketch": round(phases[-1][0], 3), "build": round(phases[-1][1], 3),
+                     "solve": round(phases[-1][2], 3)},
+        "solve": {"status": rc, "accepted_fp64": ok, "max_relres_true": max(rel_true),
+                  "sampled_rows_max_relres": sampled, "max_iters_per_lambda": per_lambda,
+                  "sum_column_iters": sum(iters), "sum_refinements": sum(refs), "rank": P.rank, "nu": P.nu},
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -37,6 +37,13 @@
  *                a.b ~ a_hi.b_hi + a_hi.b_lo + a_lo.b_hi on MFMA with float32
  *                accumulation; for m >= 16 columns the product with V uses the
  *                same three-term split.  About 16 significant bits per product.
+ *    NYS_BF16X3_D6  as NYS_BF16X3, but the distance operands are split into
+ *                three bf16 parts and the six leading products are kept
+ *                (hh + hm + mh + hl + lh + mm), about 24 bits.  The three-term
+ *                distance leaves a structured error K o (X_lo X_lo^T) of norm
+ *                about 2^-17 (d / sigma^2) |K|; when lambda is below that the
+ *                perturbed operator can be indefinite and CG diverges, so small
+ *                regularisations (lambda < ~1e-5 |K|) need this variant.
  */
 #ifndef NYS_H
 #define NYS_H
@@ -60,7 +67,7 @@ extern "C" {
 #define NYS_ENOMEM        (-5) /* workspace smaller than nys_workspace_bytes() */
 
 typedef enum { NYS_RBF = 0, NYS_LAPLACIAN = 1 } nys_kind;
-typedef enum { NYS_FP64 = 0, NYS_FP32 = 1, NYS_BF16X3 = 2 } nys_prec;
+typedef enum { NYS_FP64 = 0, NYS_FP32 = 1, NYS_BF16X3 = 2, NYS_BF16X3_D6 = 3 } nys_prec;
 
 /* Operations whose workspace can be queried. */
 typedef enum {
@@ -87,8 +94,8 @@ typedef struct {
  *    rank     out: columns of U kept (those with sigma_i^2 > 1e-14 sigma_1^2);
  *             dropped columns of U are zero and their lam_hat is 0
  *    U        device, n x r float64, orthonormal columns
- *    U32      device, n x r float32 copy of U, or NULL (needed by the FP32 and
- *             BF16X3 solves)
+ *    U32      device, n x r float32 copy of U, or NULL (filled when given; the
+ *             apply itself always works from U in float64)
  *    lam_hat  device, r float64, descending, >= 0
  *    nu       out: the shift used by the stabilised approximation
  */
@@ -109,15 +116,25 @@ typedef struct {
  *    max_iters     cap on products with A per column (paper default 1000)
  *    prec          nys_prec of the kernel product and of the CG vectors
  *                  (FP64: float64 vectors; FP32/BF16X3: float32 vectors)
- *    refine_every  FP32/BF16X3 only: every refine_every iterations the solution
- *                  is accumulated in float64 and the residual b - (K + lambda I) x
- *                  is recomputed with the float64 kernel product; 0 = only when
- *                  a column's recursive residual meets tol
- *    refine_mode   0: keep the search direction after a refinement (residual
- *                  replacement); 1: restart the recurrence (p = z)
+ *    refine_every  FP32/BF16X3 only (float64 refinement; -1 disables it and the
+ *                  columns stop on their recursive residual).  A refinement
+ *                  accumulates the column's iterate in float64, recomputes
+ *                  r = b - (K + lambda I) x with the float64 kernel product and
+ *                  accepts the column only if that true residual meets tol.
+ *                  refine_every > 0: every refine_every iterations all active
+ *                  columns are refined.  0: a column is refined when its
+ *                  recursive residual has fallen by its cycle factor since its
+ *                  last refinement, or meets tol; columns close to that point
+ *                  join the same float64 product.
+ *    refine_mode   0: after a refinement keep the search direction when the true
+ *                  residual is within 0.8x..1.25x of the recursive one, else
+ *                  restart the recurrence (p = z); 1: always restart
  *    check_true    1: after the solve compute the float64 true relative residual
  *                  of every column into info (eq. experiment-relative-residual)
  *    max_refinements  cap on refinements per column (0: 50)
+ *    refine_reduction  first cycle factor of refine_every == 0 (0: tol); later
+ *                  cycles use max(refine_reduction, min(0.5, g)) with g the
+ *                  true-residual reduction the previous cycle achieved
  */
 typedef struct {
   double tol;
@@ -127,6 +144,7 @@ typedef struct {
   int32_t refine_mode;
   int32_t check_true;
   int32_t max_refinements;
+  double refine_reduction;
 } nys_pcg_opts;
 
 /* Per-column result. */
@@ -196,8 +214,10 @@ int32_t nys_precond_build(const double *Y, const double *Q, int64_t n, int32_t r
  * P_c = U diag(lam_hat) U^T + lambdas[c] I, through the closed form
  * P_c^{-1} = U diag(1/(lam_hat + lambda_c)) U^T + (I - U U^T) / lambda_c.
  *    lambdas  device float64, m values (lambda_c > 0)
- *    R, Z     device n x m; float64 if prec == NYS_FP64 (uses U), else float32
- *             (uses U32)
+ *    R, Z     device n x m; float64 if prec == NYS_FP64, else float32
+ * The arithmetic is float64 in every case (float32 vectors are rounded once on
+ * output): for lambda far below lam_hat_1 the two terms cancel inside span(U),
+ * and a float32 evaluation would leave P^{-1} indefinite.
  * R and Z must not overlap. */
 int32_t nys_precond_apply(const nys_precond *P, const double *lambdas, int32_t prec,
                           const void *R, int32_t m, void *Z, void *ws, size_t ws_bytes, void *stream);

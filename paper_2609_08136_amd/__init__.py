@@ -18,8 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnys.so")
 
 RBF, LAPLACIAN = 0, 1
-FP64, FP32, BF16X3 = 0, 1, 2
-PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3"}
+FP64, FP32, BF16X3, BF16X3_D6 = 0, 1, 2, 3
+PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16X3_D6: "bf16x3_d6"}
 PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
@@ -42,7 +42,8 @@ class NysPrecondC(ctypes.Structure):
 
 class NysPCGOpts(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("max_iters", c_i32), ("prec", c_i32), ("refine_every", c_i32),
-                ("refine_mode", c_i32), ("check_true", c_i32), ("max_refinements", c_i32)]
+                ("refine_mode", c_i32), ("check_true", c_i32), ("max_refinements", c_i32),
+                ("refine_reduction", c_f64)]
 
 
 class NysColInfo(ctypes.Structure):
@@ -234,9 +235,10 @@ def nys_precond_apply(P: Preconditioner, lambdas, R, prec: int = FP64):
     return Z.reshape(-1) if vec else Z
 
 
-def _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements) -> NysPCGOpts:
+def _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements,
+          refine_reduction=1e-3) -> NysPCGOpts:
     return NysPCGOpts(float(tol), int(max_iters), int(prec), int(refine_every), int(refine_mode), int(check_true),
-                      int(max_refinements))
+                      int(max_refinements), float(refine_reduction))
 
 
 def _info_list(arr, count):
@@ -246,7 +248,8 @@ def _info_list(arr, count):
 
 def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | None = None, tol: float = 1e-6,
                  max_iters: int = 1000, prec: int = FP64, refine_every: int = -1, refine_mode: int = 0,
-                 check_true: bool = False, max_refinements: int = 0, workspace: torch.Tensor | None = None):
+                 check_true: bool = False, max_refinements: int = 0, workspace: torch.Tensor | None = None,
+                 refine_reduction: float = 1e-3):
     """Solve (K + lambdas[l] I) x = B[:, j] for every (l, j); column l*nrhs + j of the result.
     Returns (Xsol (n x nlam*nrhs float64), info list, status)."""
     lib = load()
@@ -264,7 +267,7 @@ def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | Non
     lam_arr = (c_f64 * nlam)(*lams)
     need = nys_workspace_bytes(OP_SOLVE, n, 0, d, P.r if P is not None else 0, m, prec)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
-    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements)
+    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements, refine_reduction)
     cs = P.c_struct() if P is not None else None
     rc = lib.nyspcg_solve(NysKernel(kind, 0, float(sigma)), X.data_ptr(), n, d, B2.data_ptr(), nrhs, lam_arr, nlam,
                           ctypes.byref(cs) if cs is not None else None, ctypes.byref(o), Xsol.data_ptr(), info,
@@ -275,7 +278,8 @@ def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | Non
 
 def nyspcg_backward(X, lam: float, xsol, gx, kind: int, sigma: float, P: Preconditioner | None = None,
                     tol: float = 1e-10, max_iters: int = 1000, prec: int = FP64, refine_every: int = -1,
-                    refine_mode: int = 0, check_true: bool = False, max_refinements: int = 0):
+                    refine_mode: int = 0, check_true: bool = False, max_refinements: int = 0,
+                    refine_reduction: float = 1e-3):
     """Adjoint solve (K + lam I) a = gx; returns (a, dL/dlambda, dL/dsigma, info)."""
     lib = load()
     _need_cuda(X, torch.float64, "X")
@@ -288,7 +292,7 @@ def nyspcg_backward(X, lam: float, xsol, gx, kind: int, sigma: float, P: Precond
     dl, ds = c_f64(0.0), c_f64(0.0)
     info = (NysColInfo * 1)()
     ws = _workspace(nys_workspace_bytes(OP_BACKWARD, n, 0, d, P.r if P is not None else 0, 1, prec), X.device)
-    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements)
+    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements, refine_reduction)
     cs = P.c_struct() if P is not None else None
     rc = lib.nyspcg_backward(NysKernel(kind, 0, float(sigma)), X.data_ptr(), n, d, float(lam), xs.data_ptr(),
                              g.data_ptr(), ctypes.byref(cs) if cs is not None else None, ctypes.byref(o),

@@ -3,6 +3,8 @@
 // the PCG driver with column compaction and float64 refinement, backward).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -27,8 +29,8 @@ int32_t einval(const std::string &m) {
   set_error(m);
   return NYS_EINVAL;
 }
-bool valid_prec(int p) { return p == NYS_FP64 || p == NYS_FP32 || p == NYS_BF16X3; }
-int max_dim(int prec) { return prec == NYS_BF16X3 ? 82 : 62; }
+bool valid_prec(int p) { return p == NYS_FP64 || p == NYS_FP32 || p == NYS_BF16X3 || p == NYS_BF16X3_D6; }
+int max_dim(int prec) { return prec == NYS_BF16X3 ? 82 : (prec == NYS_BF16X3_D6 ? 41 : 62); }
 size_t elem_bytes(int prec) { return prec == NYS_FP64 ? 8 : 4; }
 
 int32_t check_kernel(const nys_kernel &k) {
@@ -185,6 +187,8 @@ struct SolvePlan {
   double *lam = nullptr, *rho = nullptr, *ab = nullptr, *rr = nullptr, *tmpc = nullptr;
   double *red = nullptr;
   int *bcol = nullptr, *restart = nullptr, *flag = nullptr, *idx = nullptr, *idx2 = nullptr;
+  int *bcol2 = nullptr;
+  double *lam2 = nullptr;
   char *pws = nullptr;
   size_t pws_bytes = 0;
 };
@@ -222,6 +226,8 @@ void plan_solve(SolvePlan &p, int64_t n, int d, int r, int m, int prec, bool ref
   p.flag = ws.take<int>(m);
   p.idx = ws.take<int>(m);
   p.idx2 = ws.take<int>(m);
+  p.bcol2 = ws.take<int>(m);
+  p.lam2 = ws.take<double>(m);
   if (r > 0) {
     size_t mx = 0;
     for (int mm = 1; mm <= m; ++mm) mx = std::max(mx, precond_apply_scratch_bytes(n, r, mm, prec));
@@ -254,269 +260,14 @@ int32_t apply_precond_or_copy(const nys_precond *P, SolvePlan &sp, const T *R, i
   return precond_apply_impl<T>(*P, sp.lam, R, m, Z, a, s);
 }
 
-// The PCG driver.  Columns are kept compacted: slot s < ma holds original
-// column orig[s]; converged columns are written to Xsol and removed.
-template <class T>
-int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d, const double *B, int nrhs,
-                      const double *lambdas, int nlam, const nys_precond *P, const nys_pcg_opts &o,
-                      double *Xsol, nys_col_info *info, SolvePlan &sp, hipStream_t s) {
-  const int mtot = nlam * nrhs;
-  const int prec = sp.prec;
-  const bool lowp = sp.lowp;
-  const bool refine = lowp && o.refine_every >= 0;
-  const int max_refs = o.max_refinements > 0 ? o.max_refinements : 50;
-  T *X = reinterpret_cast<T *>(sp.X), *R = reinterpret_cast<T *>(sp.R), *Z = reinterpret_cast<T *>(sp.Z);
-  T *Pd = reinterpret_cast<T *>(sp.P), *W = reinterpret_cast<T *>(sp.W), *Sp = reinterpret_cast<T *>(sp.Spare);
-  double *X64 = sp.X64, *R64 = sp.R64, *Sp64 = sp.Spare64;
-
-  // points
-  NYS_RETURN_IF(prep_points(sp.kv, k, prec, Xpts, Xpts, d, s));
-  if (sp.need64) NYS_RETURN_IF(prep_points(sp.kv64, k, NYS_FP64, Xpts, Xpts, d, s));
-  KmvBufs &k64 = sp.need64 ? sp.kv64 : sp.kv;
-
-  // per-column setup
-  std::vector<int> orig(mtot), bcol_h(mtot);
-  std::vector<double> lam_h(mtot), bb(mtot);
-  for (int c = 0; c < mtot; ++c) {
-    orig[c] = c;
-    bcol_h[c] = c % nrhs;
-    lam_h[c] = lambdas[c / nrhs];
-    info[c] = nys_col_info{0, 0, NYS_NOT_CONVERGED, 0, 1.0, -1.0};
-  }
-  NYS_CHECK_HIP(hipMemcpyAsync(sp.bcol, bcol_h.data(), sizeof(int) * mtot, hipMemcpyHostToDevice, s));
-  NYS_CHECK_HIP(hipMemcpyAsync(sp.lam, lam_h.data(), sizeof(double) * mtot, hipMemcpyHostToDevice, s));
-  NYS_CHECK_HIP(hipMemsetAsync(sp.restart, 0, sizeof(int) * mtot, s));
-  NYS_CHECK_HIP(hipMemsetAsync(sp.flag, 0, sizeof(int) * mtot, s));
-  NYS_RETURN_IF(init_rhs<T>(B, nrhs, sp.bcol, R, X, n, mtot, s));
-  if (X64) NYS_RETURN_IF(launch_fill(X64, 0.0, n * (int64_t)mtot, s));
-  NYS_RETURN_IF(colred<T>(0, R, R, nullptr, nullptr, n, mtot, nullptr, sp.red, s));
-  NYS_RETURN_IF(colfinal(sp.red, n, mtot, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
-  NYS_CHECK_HIP(hipMemcpyAsync(bb.data(), sp.tmpc, sizeof(double) * mtot, hipMemcpyDeviceToHost, s));
-  NYS_CHECK_HIP(hipStreamSynchronize(s));
-  for (int c = 0; c < mtot; ++c)
-    if (!std::isfinite(bb[c])) {
-      set_error("nyspcg_solve: NaN or Inf in the right-hand side");
-      return NYS_ENUMERIC;
-    }
-
-  int ma = mtot;
-  std::vector<double> bb_s(bb);     // per slot
-  std::vector<double> rr_h(mtot), rt_h(mtot);
-  std::vector<int> flag_h(mtot), it_s(mtot, 0), ref_s(mtot, 0), restart_h(mtot, 0);
-  std::vector<int> keep, done, done_orig;
-  bool breakdown = false;
-
-  // compaction: keep slots listed in `keep`, in order
-  auto compact = [&](const std::vector<int> &kp) -> int32_t {
-    const int mn = (int)kp.size();
-    if (mn == ma) return NYS_OK;
-    if (mn > 0) {
-      NYS_CHECK_HIP(hipMemcpyAsync(sp.idx, kp.data(), sizeof(int) * mn, hipMemcpyHostToDevice, s));
-      NYS_RETURN_IF(gather_cols<T>(X, ma, sp.idx, mn, Sp, n, s));
-      std::swap(X, Sp);
-      NYS_RETURN_IF(gather_cols<T>(R, ma, sp.idx, mn, Sp, n, s));
-      std::swap(R, Sp);
-      NYS_RETURN_IF(gather_cols<T>(Pd, ma, sp.idx, mn, Sp, n, s));
-      std::swap(Pd, Sp);
-      if (X64) {
-        NYS_RETURN_IF(gather_cols<double>(X64, ma, sp.idx, mn, Sp64, n, s));
-        std::swap(X64, Sp64);
-      }
-      NYS_RETURN_IF(gather_cols<double>(sp.rho, ma, sp.idx, mn, sp.tmpc, 1, s));
-      NYS_CHECK_HIP(hipMemcpyAsync(sp.rho, sp.tmpc, sizeof(double) * mn, hipMemcpyDeviceToDevice, s));
-    }
-    std::vector<int> o2(mn), b2(mn);
-    std::vector<double> l2(mn), bb2(mn);
-    std::vector<int> it2(mn), rf2(mn);
-    for (int q = 0; q < mn; ++q) {
-      o2[q] = orig[kp[q]];
-      b2[q] = bcol_h[kp[q]];
-      l2[q] = lam_h[kp[q]];
-      bb2[q] = bb_s[kp[q]];
-      it2[q] = it_s[kp[q]];
-      rf2[q] = ref_s[kp[q]];
-    }
-    orig = o2;
-    bcol_h = b2;
-    lam_h = l2;
-    bb_s = bb2;
-    it_s = it2;
-    ref_s = rf2;
-    ma = mn;
-    if (mn > 0) {
-      NYS_CHECK_HIP(hipMemcpyAsync(sp.bcol, bcol_h.data(), sizeof(int) * mn, hipMemcpyHostToDevice, s));
-      NYS_CHECK_HIP(hipMemcpyAsync(sp.lam, lam_h.data(), sizeof(double) * mn, hipMemcpyHostToDevice, s));
-    }
-    NYS_CHECK_HIP(hipStreamSynchronize(s));  // host index vectors may go out of scope
-    return NYS_OK;
-  };
-  // write finished slots to Xsol
-  auto finish = [&](const std::vector<int> &slots) -> int32_t {
-    if (slots.empty()) return NYS_OK;
-    std::vector<int> og(slots.size());
-    for (size_t q = 0; q < slots.size(); ++q) og[q] = orig[slots[q]];
-    NYS_CHECK_HIP(hipMemcpyAsync(sp.idx, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, s));
-    NYS_CHECK_HIP(hipMemcpyAsync(sp.idx2, og.data(), sizeof(int) * og.size(), hipMemcpyHostToDevice, s));
-    NYS_RETURN_IF(scatter_sol<T>(X, X64, ma, sp.idx, sp.idx2, (int)slots.size(), Xsol, mtot, n, s));
-    // make the host vectors safe to reuse before the copies complete
-    NYS_CHECK_HIP(hipStreamSynchronize(s));
-    return NYS_OK;
-  };
-
-  // zero right-hand sides: x = 0 after 0 iterations
-  {
-    std::vector<int> z, kp;
-    for (int c = 0; c < ma; ++c) (bb_s[c] == 0.0 ? z : kp).push_back(c);
-    for (int c : z) {
-      info[orig[c]].status = NYS_OK;
-      info[orig[c]].relres_recursive = 0.0;
-      info[orig[c]].relres_true = 0.0;
-    }
-    NYS_RETURN_IF(finish(z));
-    NYS_RETURN_IF(compact(kp));
-  }
-  if (ma > 0 && o.max_iters > 0) {
-    NYS_RETURN_IF(apply_precond_or_copy<T>(P, sp, R, ma, Z, n, s));
-    NYS_RETURN_IF(colred<T>(0, R, Z, nullptr, nullptr, n, ma, nullptr, sp.red, s));
-    NYS_RETURN_IF(colfinal(sp.red, n, ma, 0, sp.rho, nullptr, nullptr, nullptr, nullptr, s));
-    NYS_CHECK_HIP(hipMemcpyAsync(Pd, Z, sizeof(T) * n * ma, hipMemcpyDeviceToDevice, s));
-  }
-  const double tol = o.tol;
-  int iter = 0;
-  while (ma > 0) {
-    if (iter >= o.max_iters) break;
-    ++iter;
-    // w = K p + lambda p ; alpha = rho / p^T w
-    NYS_RETURN_IF(run_kmv(sp.kv, k, 0, prec, 1, Pd, ma, ma, W, ma, 1.0, 0.0, s));
-    NYS_RETURN_IF(colred<T>(1, Pd, W, nullptr, nullptr, n, ma, sp.lam, sp.red, s));
-    NYS_RETURN_IF(colfinal(sp.red, n, ma, 1, nullptr, sp.rho, sp.ab, nullptr, sp.flag, s));
-    // x += alpha p ; r -= alpha w ; rr = r^T r
-    NYS_RETURN_IF(colred<T>(2, Pd, W, X, R, n, ma, sp.ab, sp.red, s));
-    NYS_RETURN_IF(colfinal(sp.red, n, ma, 0, sp.rr, nullptr, nullptr, nullptr, nullptr, s));
-    NYS_CHECK_HIP(hipMemcpyAsync(rr_h.data(), sp.rr, sizeof(double) * ma, hipMemcpyDeviceToHost, s));
-    NYS_CHECK_HIP(hipMemcpyAsync(flag_h.data(), sp.flag, sizeof(int) * ma, hipMemcpyDeviceToHost, s));
-    NYS_CHECK_HIP(hipStreamSynchronize(s));
-
-    std::vector<char> conv(ma, 0), stop(ma, 0);
-    bool any_conv = false, any_restart = false;
-    for (int q = 0; q < ma; ++q) {
-      it_s[q] += 1;
-      const double rel = std::sqrt(std::max(rr_h[q], 0.0) / bb_s[q]);
-      info[orig[q]].iters = it_s[q];
-      info[orig[q]].relres_recursive = rel;
-      if (flag_h[q] || !std::isfinite(rel)) {
-        stop[q] = 1;
-        breakdown = true;
-        info[orig[q]].status = NYS_ENOTPD;
-        continue;
-      }
-      if (rel <= tol) {
-        conv[q] = 1;
-        any_conv = true;
-      }
-    }
-    const bool periodic = refine && o.refine_every > 0 && (iter % o.refine_every == 0);
-    if (refine && (any_conv || periodic)) {
-      // float64 residual replacement: x64 += x, r = b - (K + lambda I) x64
-      NYS_RETURN_IF(flush_x(reinterpret_cast<float *>(X), X64, n * (int64_t)ma, s));
-      NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, X64, ma, ma, R64, ma, 1.0, 0.0, s));
-      NYS_RETURN_IF(residual64(B, nrhs, sp.bcol, sp.lam, X64, R64, reinterpret_cast<float *>(R), n, ma, s));
-      NYS_RETURN_IF(colred<double>(0, R64, R64, nullptr, nullptr, n, ma, nullptr, sp.red, s));
-      NYS_RETURN_IF(colfinal(sp.red, n, ma, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
-      NYS_CHECK_HIP(hipMemcpyAsync(rt_h.data(), sp.tmpc, sizeof(double) * ma, hipMemcpyDeviceToHost, s));
-      NYS_CHECK_HIP(hipStreamSynchronize(s));
-      for (int q = 0; q < ma; ++q) {
-        if (stop[q]) continue;
-        ref_s[q] += 1;
-        const double rel = std::sqrt(std::max(rt_h[q], 0.0) / bb_s[q]);
-        info[orig[q]].refinements = ref_s[q];
-        info[orig[q]].relres_true = rel;
-        conv[q] = rel <= tol;
-        restart_h[q] = (o.refine_mode == 1) ? 1 : 0;
-        if (restart_h[q]) any_restart = true;
-        if (!conv[q] && ref_s[q] >= max_refs) stop[q] = 1;
-      }
-    }
-    // collect finished columns
-    std::vector<int> fin, kp;
-    for (int q = 0; q < ma; ++q) {
-      const bool over = it_s[q] >= o.max_iters;
-      if (conv[q]) info[orig[q]].status = NYS_OK;
-      if (conv[q] || stop[q] || over) fin.push_back(q);
-      else kp.push_back(q);
-    }
-    if (!fin.empty()) {
-      NYS_RETURN_IF(finish(fin));
-      std::vector<int> rs(kp.size());
-      for (size_t q = 0; q < kp.size(); ++q) rs[q] = restart_h[kp[q]];
-      NYS_RETURN_IF(compact(kp));
-      restart_h.assign(mtot, 0);
-      for (size_t q = 0; q < rs.size(); ++q) restart_h[q] = rs[q];
-      any_restart = false;
-      for (int q = 0; q < ma; ++q) any_restart |= restart_h[q] != 0;
-      NYS_CHECK_HIP(hipMemsetAsync(sp.flag, 0, sizeof(int) * std::max(ma, 1), s));
-    }
-    if (ma == 0) break;
-    if (any_restart) {
-      NYS_CHECK_HIP(hipMemcpyAsync(sp.restart, restart_h.data(), sizeof(int) * ma, hipMemcpyHostToDevice, s));
-      NYS_CHECK_HIP(hipStreamSynchronize(s));
-    }
-    // z = P^{-1} r ; beta = r^T z / rho ; p = z + beta p
-    NYS_RETURN_IF(apply_precond_or_copy<T>(P, sp, R, ma, Z, n, s));
-    NYS_RETURN_IF(colred<T>(0, R, Z, nullptr, nullptr, n, ma, nullptr, sp.red, s));
-    NYS_RETURN_IF(colfinal(sp.red, n, ma, 2, nullptr, sp.rho, sp.ab, any_restart ? sp.restart : nullptr,
-                           nullptr, s));
-    NYS_RETURN_IF(p_update<T>(Pd, Z, sp.ab, n, ma, s));
-    if (any_restart) {
-      NYS_CHECK_HIP(hipMemsetAsync(sp.restart, 0, sizeof(int) * ma, s));
-      std::fill(restart_h.begin(), restart_h.end(), 0);
-    }
-  }
-  // columns still active hit the iteration cap
-  if (ma > 0) {
-    std::vector<int> all(ma);
-    for (int q = 0; q < ma; ++q) all[q] = q;
-    if (refine) {
-      NYS_RETURN_IF(flush_x(reinterpret_cast<float *>(X), X64, n * (int64_t)ma, s));
-      NYS_CHECK_HIP(hipMemsetAsync(X, 0, sizeof(T) * n * ma, s));
-    }
-    NYS_RETURN_IF(finish(all));
-  }
-  // optional float64 true residual of every column
-  if (o.check_true && R64) {
-    NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, Xsol, mtot, mtot, R64, mtot, 1.0, 0.0, s));
-    std::vector<int> bc(mtot);
-    std::vector<double> lm(mtot);
-    for (int c = 0; c < mtot; ++c) {
-      bc[c] = c % nrhs;
-      lm[c] = lambdas[c / nrhs];
-    }
-    NYS_CHECK_HIP(hipMemcpyAsync(sp.bcol, bc.data(), sizeof(int) * mtot, hipMemcpyHostToDevice, s));
-    NYS_CHECK_HIP(hipMemcpyAsync(sp.lam, lm.data(), sizeof(double) * mtot, hipMemcpyHostToDevice, s));
-    NYS_RETURN_IF(residual64(B, nrhs, sp.bcol, sp.lam, Xsol, R64, nullptr, n, mtot, s));
-    NYS_RETURN_IF(colred<double>(0, R64, R64, nullptr, nullptr, n, mtot, nullptr, sp.red, s));
-    NYS_RETURN_IF(colfinal(sp.red, n, mtot, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
-    std::vector<double> rt(mtot);
-    NYS_CHECK_HIP(hipMemcpyAsync(rt.data(), sp.tmpc, sizeof(double) * mtot, hipMemcpyDeviceToHost, s));
-    NYS_CHECK_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < mtot; ++c)
-      info[c].relres_true = bb[c] > 0 ? std::sqrt(std::max(rt[c], 0.0) / bb[c]) : 0.0;
-  }
-  NYS_CHECK_HIP(hipStreamSynchronize(s));
-  if (breakdown) {
-    set_error("nyspcg_solve: PCG breakdown (p^T A p <= 0 or non-finite) in at least one column");
-    return NYS_ENOTPD;
-  }
-  for (int c = 0; c < mtot; ++c)
-    if (info[c].status != NYS_OK) return NYS_NOT_CONVERGED;
-  return NYS_OK;
-}
+// The PCG driver (solve_columns).
+#include "solve_impl.h"
 
 int32_t check_precond(const nys_precond *P, int64_t n, int prec) {
   if (!P) return NYS_OK;
   if (P->n != n) return einval("preconditioner built for a different n");
   if (P->r < 1 || !P->U || !P->lam_hat) return einval("preconditioner buffers missing");
-  if (prec != NYS_FP64 && !P->U32) return einval("FP32/BF16X3 solves need the float32 copy U32");
+  (void)prec;
   return NYS_OK;
 }
 

@@ -12,12 +12,12 @@ constexpr int GT = 64;   // output tile
 constexpr int GK = 16;   // k slice
 
 // --------------------------------------------------------------- C = A^T B
-template <class T>
-__global__ __launch_bounds__(256) void gemm_tn_kernel(const T *A, int lda, const T *B, int ldb,
+template <class TA, class TB, class TO>
+__global__ __launch_bounds__(256) void gemm_tn_kernel(const TA *A, int lda, const TB *B, int ldb,
                                                       int64_t n, int p, int q, int64_t rows_per,
-                                                      T *out, int ldo, int64_t zstride) {
-  __shared__ T As[GK][GT + 1];
-  __shared__ T Bs[GK][GT + 1];
+                                                      TO *out, int ldo, int64_t zstride) {
+  __shared__ TA As[GK][GT + 1];
+  __shared__ TB Bs[GK][GT + 1];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int p0 = blockIdx.x * GT, q0 = blockIdx.y * GT;
   const int64_t r0 = (int64_t)blockIdx.z * rows_per;
@@ -27,13 +27,14 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(const T *A, int lda, const
     for (int e = threadIdx.x; e < GK * GT; e += 256) {
       int kk = e / GT, c = e - kk * GT;
       int64_t row = k0 + kk;
-      As[kk][c] = (row < r1 && p0 + c < p) ? A[row * lda + p0 + c] : (T)0;
-      Bs[kk][c] = (row < r1 && q0 + c < q) ? B[row * ldb + q0 + c] : (T)0;
+      As[kk][c] = (row < r1 && p0 + c < p) ? A[row * lda + p0 + c] : (TA)0;
+      Bs[kk][c] = (row < r1 && q0 + c < q) ? B[row * ldb + q0 + c] : (TB)0;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GK; ++kk) {
-      T a[4], b[4];
+      TA a[4];
+      TB b[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         a[u] = As[kk][ty * 4 + u];
@@ -46,13 +47,13 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(const T *A, int lda, const
     }
     __syncthreads();
   }
-  T *o = out + (int64_t)blockIdx.z * zstride;
+  TO *o = out + (int64_t)blockIdx.z * zstride;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       int i = p0 + ty * 4 + u, j = q0 + tx * 4 + v;
-      if (i < p && j < q) o[(int64_t)i * ldo + j] = (T)acc[u][v];
+      if (i < p && j < q) o[(int64_t)i * ldo + j] = (TO)acc[u][v];
     }
 }
 
@@ -73,19 +74,19 @@ int gemm_tn_splits(int64_t n, int p, int q) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(want, maxs));
 }
 
-template <class T>
-int32_t gemm_tn(const T *A, int lda, const T *B, int ldb, int64_t n, int p, int q, T *C, int ldc,
-                T *partial, int splits, hipStream_t s) {
+template <class TA, class TB, class T>
+static int32_t gemm_tn_impl(const TA *A, int lda, const TB *B, int ldb, int64_t n, int p, int q, T *C,
+                            int ldc, T *partial, int splits, hipStream_t s) {
   const int64_t rows_per = round_up(ceil_div(n, splits), GK);
   const int z = (int)ceil_div(n, rows_per);
   dim3 grid((unsigned)ceil_div(p, GT), (unsigned)ceil_div(q, GT), (unsigned)std::max(z, 1));
   if (z <= 1) {
-    hipLaunchKernelGGL(gemm_tn_kernel<T>, grid, dim3(256), 0, s, A, lda, B, ldb, n, p, q, rows_per, C,
-                       ldc, (int64_t)0);
+    hipLaunchKernelGGL((gemm_tn_kernel<TA, TB, T>), grid, dim3(256), 0, s, A, lda, B, ldb, n, p, q, rows_per,
+                       C, ldc, (int64_t)0);
     NYS_LAUNCH_CHECK();
     return NYS_OK;
   }
-  hipLaunchKernelGGL(gemm_tn_kernel<T>, grid, dim3(256), 0, s, A, lda, B, ldb, n, p, q, rows_per,
+  hipLaunchKernelGGL((gemm_tn_kernel<TA, TB, T>), grid, dim3(256), 0, s, A, lda, B, ldb, n, p, q, rows_per,
                      partial, q, (int64_t)p * q);
   NYS_LAUNCH_CHECK();
   const int64_t tot = (int64_t)p * q;
@@ -95,11 +96,23 @@ int32_t gemm_tn(const T *A, int lda, const T *B, int ldb, int64_t n, int p, int 
   return NYS_OK;
 }
 
-// --------------------------------------------------------------- C = A B (+ R * rscale)
 template <class T>
+int32_t gemm_tn(const T *A, int lda, const T *B, int ldb, int64_t n, int p, int q, T *C, int ldc,
+                T *partial, int splits, hipStream_t s) {
+  return gemm_tn_impl<T, T, T>(A, lda, B, ldb, n, p, q, C, ldc, partial, splits, s);
+}
+
+int32_t gemm_tn_df(const double *A, int lda, const float *B, int ldb, int64_t n, int p, int q, double *C,
+                   int ldc, double *partial, int splits, hipStream_t s) {
+  return gemm_tn_impl<double, float, double>(A, lda, B, ldb, n, p, q, C, ldc, partial, splits, s);
+}
+
+// --------------------------------------------------------------- C = A B (+ R * rscale)
+// Arithmetic in T; the output C and the epilogue operand R have type TC.
+template <class T, class TC>
 __global__ __launch_bounds__(256) void gemm_nn_kernel(const T *A, int lda, const T *B, int ldb,
-                                                      int64_t n, int p, int q, T *C, int ldc,
-                                                      int epi, const T *R, int ldr,
+                                                      int64_t n, int p, int q, TC *C, int ldc,
+                                                      int epi, const TC *R, int ldr,
                                                       const double *rscale) {
   __shared__ T As[GK][GT + 1];   // As[k][row]
   __shared__ T Bs[GK][GT + 1];   // Bs[k][col]
@@ -139,8 +152,8 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const T *A, int lda, const
       int j = q0 + tx * 4 + v;
       if (i < n && j < q) {
         T val = acc[u][v];
-        if (epi == 1) val += R[i * ldr + j] * (T)rscale[j];
-        C[i * ldc + j] = val;
+        if (epi == 1) val += (T)R[i * ldr + j] * (T)rscale[j];
+        C[i * ldc + j] = (TC)val;
       }
     }
 }
@@ -150,8 +163,18 @@ int32_t gemm_nn(const T *A, int lda, const T *B, int ldb, int64_t n, int p, int 
                 int epi, const T *R, int ldr, const double *rscale, hipStream_t s) {
   if (n <= 0 || q <= 0) return NYS_OK;
   dim3 grid((unsigned)ceil_div(q, GT), (unsigned)ceil_div(n, GT));
-  hipLaunchKernelGGL(gemm_nn_kernel<T>, grid, dim3(256), 0, s, A, lda, B, ldb, n, p, q, C, ldc, epi, R,
+  hipLaunchKernelGGL((gemm_nn_kernel<T, T>), grid, dim3(256), 0, s, A, lda, B, ldb, n, p, q, C, ldc, epi, R,
                      ldr, rscale);
+  NYS_LAUNCH_CHECK();
+  return NYS_OK;
+}
+
+int32_t gemm_nn_dd_f(const double *A, int lda, const double *B, int ldb, int64_t n, int p, int q, float *C,
+                     int ldc, const float *R, int ldr, const double *rscale, hipStream_t s) {
+  if (n <= 0 || q <= 0) return NYS_OK;
+  dim3 grid((unsigned)ceil_div(q, GT), (unsigned)ceil_div(n, GT));
+  hipLaunchKernelGGL((gemm_nn_kernel<double, float>), grid, dim3(256), 0, s, A, lda, B, ldb, n, p, q, C, ldc, 1,
+                     R, ldr, rscale);
   NYS_LAUNCH_CHECK();
   return NYS_OK;
 }

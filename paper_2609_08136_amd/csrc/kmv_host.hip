@@ -11,6 +11,7 @@ namespace nys {
 // ------------------------------------------------------------------ packing
 int packed_kp(int d, int prec) {
   if (prec == NYS_BF16X3) return (int)round_up(3 * d + 6, 32);
+  if (prec == NYS_BF16X3_D6) return (int)round_up(6 * d + 6, 32);
   return (int)round_up(d + 2, 4);
 }
 size_t packed_elem_bytes(int prec) {
@@ -83,7 +84,7 @@ __device__ inline void split_bf16(double v, int parts, u16 *out) {
   }
 }
 
-template <int PREC, int SIDE>
+template <int PREC, int SIDE, int NT = 3>
 __global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu, double kappa,
                             void *out, int Kp, int64_t n_pad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,27 +119,42 @@ __global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu,
       const u16 one = bf16_bits_rne(1.0f);
       for (int l = 0; l < d; ++l) {
         double v = X[i * d + l] - mu[l];
-        u16 hl[2];
-        if (SIDE == SIDE_COL) {
-          split_bf16(2.0 * kappa * v, 2, hl);   // [y_hi | y_lo | y_hi]
-          o[l] = hl[0];
-          o[d + l] = hl[1];
-          o[2 * d + l] = hl[0];
+        if constexpr (NT == 3) {
+          u16 hl[2];
+          if (SIDE == SIDE_COL) {
+            split_bf16(2.0 * kappa * v, 2, hl);   // [y_hi | y_lo | y_hi]
+            o[l] = hl[0];
+            o[d + l] = hl[1];
+            o[2 * d + l] = hl[0];
+          } else {
+            split_bf16(v, 2, hl);                 // [x_hi | x_hi | x_lo]
+            o[l] = hl[0];
+            o[d + l] = hl[0];
+            o[2 * d + l] = hl[1];
+          }
         } else {
-          split_bf16(v, 2, hl);                 // [x_hi | x_hi | x_lo]
-          o[l] = hl[0];
-          o[d + l] = hl[0];
-          o[2 * d + l] = hl[1];
+          // three parts h, m, l; products hh + hm + mh + hl + lh + mm
+          u16 p3[3];
+          if (SIDE == SIDE_COL) {
+            split_bf16(2.0 * kappa * v, 3, p3);   // [h | h | m | h | l | m]
+            o[l] = p3[0]; o[d + l] = p3[0]; o[2 * d + l] = p3[1];
+            o[3 * d + l] = p3[0]; o[4 * d + l] = p3[2]; o[5 * d + l] = p3[1];
+          } else {
+            split_bf16(v, 3, p3);                 // [h | m | h | l | h | m]
+            o[l] = p3[0]; o[d + l] = p3[1]; o[2 * d + l] = p3[0];
+            o[3 * d + l] = p3[2]; o[4 * d + l] = p3[0]; o[5 * d + l] = p3[1];
+          }
         }
       }
       u16 b3[3];
       split_bf16(-kappa * s, 3, b3);
+      const int o0 = NT * d;
       if (SIDE == SIDE_COL) {                   // [1 1 1 | b_hi b_mid b_lo]
-        o[3 * d + 0] = one; o[3 * d + 1] = one; o[3 * d + 2] = one;
-        o[3 * d + 3] = b3[0]; o[3 * d + 4] = b3[1]; o[3 * d + 5] = b3[2];
+        o[o0 + 0] = one; o[o0 + 1] = one; o[o0 + 2] = one;
+        o[o0 + 3] = b3[0]; o[o0 + 4] = b3[1]; o[o0 + 5] = b3[2];
       } else {                                  // [a_hi a_mid a_lo | 1 1 1]
-        o[3 * d + 0] = b3[0]; o[3 * d + 1] = b3[1]; o[3 * d + 2] = b3[2];
-        o[3 * d + 3] = one; o[3 * d + 4] = one; o[3 * d + 5] = one;
+        o[o0 + 0] = b3[0]; o[o0 + 1] = b3[1]; o[o0 + 2] = b3[2];
+        o[o0 + 3] = one; o[o0 + 4] = one; o[o0 + 5] = one;
       }
     }
   }
@@ -152,7 +168,13 @@ int32_t launch_pack(const double *X, int64_t n, int d, const double *mu, const n
 #define NYS_PACK(P, S) hipLaunchKernelGGL((pack_kernel<P, S>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad)
   if (prec == NYS_FP64) { if (side == SIDE_COL) NYS_PACK(NYS_FP64, SIDE_COL); else NYS_PACK(NYS_FP64, SIDE_ROW); }
   else if (prec == NYS_FP32) { if (side == SIDE_COL) NYS_PACK(NYS_FP32, SIDE_COL); else NYS_PACK(NYS_FP32, SIDE_ROW); }
-  else { if (side == SIDE_COL) NYS_PACK(NYS_BF16X3, SIDE_COL); else NYS_PACK(NYS_BF16X3, SIDE_ROW); }
+  else if (prec == NYS_BF16X3) { if (side == SIDE_COL) NYS_PACK(NYS_BF16X3, SIDE_COL); else NYS_PACK(NYS_BF16X3, SIDE_ROW); }
+  else {
+    if (side == SIDE_COL)
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_COL, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+    else
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_ROW, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+  }
 #undef NYS_PACK
   NYS_LAUNCH_CHECK();
   return NYS_OK;
@@ -219,6 +241,7 @@ static int small_r_for(int prec, int mm) {
 
 KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   (void)Kp;
+  prec = kernel_prec(prec);
   KmvPlan p;
   const int mm_cap = prec == NYS_FP64 ? 8 : 16;
   Override ov;
@@ -265,6 +288,7 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
 
 void kmv_scratch_sizes(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec,
                        size_t *partial_bytes, size_t *vsplit_elems) {
+  prec = kernel_prec(prec);
   const size_t fb = prec == NYS_FP64 ? 8 : 4;
   *partial_bytes = p.splits > 1 ? (size_t)p.splits * nr * m * fb : 0;
   *vsplit_elems = (p.path == 1 && prec == NYS_BF16X3) ? (size_t)ceil_div(nc, 32) * p.m_pad * 32 : 0;
@@ -284,7 +308,7 @@ void kmv_reserve(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec, Aren
 }
 
 static int ksmax_for(int prec, int Kp) {
-  if (prec == NYS_BF16X3) {
+  if (kernel_prec(prec) == NYS_BF16X3) {
     int ks = Kp / 32;
     return ks <= 2 ? 2 : (ks <= 4 ? 4 : (ks <= 8 ? 8 : -1));
   }
@@ -297,6 +321,7 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, c
                 int ldo, double alpha, double beta, void *partial, void *vhi, void *vlo,
                 hipStream_t s) {
   if (m <= 0 || rows.n <= 0) return NYS_OK;
+  prec = kernel_prec(prec);
   const int ksmax = ksmax_for(prec, rows.Kp);
   if (ksmax < 0) {
     set_error("kernel_matvec: dimension too large for the tile kernels");

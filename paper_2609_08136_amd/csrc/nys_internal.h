@@ -84,6 +84,10 @@ struct Packed {
   int prec = 0;
 };
 
+// The tile kernels run BF16X3_D6 with the BF16X3 instantiations (only the
+// packing differs: six distance terms instead of three).
+inline int kernel_prec(int prec) { return prec == NYS_BF16X3_D6 ? NYS_BF16X3 : prec; }
+
 int packed_kp(int d, int prec);
 size_t packed_elem_bytes(int prec);
 double kernel_kappa(const nys_kernel &k, int prec);
@@ -134,6 +138,12 @@ template <class T>
 int32_t gemm_tn(const T *A, int lda, const T *B, int ldb, int64_t n, int p, int q, T *C,
                 int ldc, T *partial, int splits, hipStream_t s);
 int gemm_tn_splits(int64_t n, int p, int q);
+// Mixed: C (double) = A^T B with A double and B float (products and sums in float64).
+int32_t gemm_tn_df(const double *A, int lda, const float *B, int ldb, int64_t n, int p, int q, double *C,
+                   int ldc, double *partial, int splits, hipStream_t s);
+// Mixed: C (float) = A B + R * rscale[col], arithmetic in float64, R float.
+int32_t gemm_nn_dd_f(const double *A, int lda, const double *B, int ldb, int64_t n, int p, int q, float *C,
+                     int ldc, const float *R, int ldr, const double *rscale, hipStream_t s);
 
 // C[n x q] = A[n x p] B[p x q] (+ epilogue): epi 0: C = AB; 1: C = AB + R * rscale[col]
 template <class T>

@@ -14,9 +14,10 @@ ColRedShape colred_shape(int64_t n, int m);
 // op 0: partial_c = a_c . b_c
 // op 1: b += coef_c a (W += lambda P), partial_c = a_c . b_c
 // op 2: X += coef_c a, R -= coef_c b, partial_c = R_c . R_c
+// op 3: as op 2 with the iterate accumulated in float64 (X64 += coef_c a)
 template <class T>
 int32_t colred(int op, const T *a, T *b, T *X, T *R, int64_t n, int m, const double *coef,
-               double *partial, hipStream_t s);
+               double *partial, hipStream_t s, double *X64 = nullptr);
 int32_t colfinal(const double *partial, int64_t n, int m, int mode, double *out, double *rho,
                  double *ab, const int *restart, int *flag, hipStream_t s);
 
@@ -32,6 +33,9 @@ int32_t scatter_sol(const T *X, const double *X64, int m, const int *slots, cons
                     double *Xsol, int mtot, int64_t n, hipStream_t s);
 template <class T>
 int32_t gather_cols(const T *src, int m_old, const int *keep, int m_new, T *dst, int64_t n, hipStream_t s);
+
+// dst[:, idx[k]] = (float) src[:, k]   (src n x ns double, dst n x m float)
+int32_t scatter_cols_d2f(const double *src, int ns, const int *idx, float *dst, int m, int64_t n, hipStream_t s);
 
 size_t precond_apply_scratch_bytes(int64_t n, int r, int m, int prec);
 

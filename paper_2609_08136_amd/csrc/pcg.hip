@@ -29,10 +29,11 @@ ColRedShape colred_shape(int64_t n, int m) {
 
 // op 0: partial = sum a*b;  op 1: W += lam P, partial = sum P*W (a=P, b=W);
 // op 2: X += alpha P, R -= alpha W, partial = sum R*R (a=P, b=W, X, R)
+// op 3: as op 2 but the iterate is float64 (X64 += alpha P)
 template <class T, int OP>
 __global__ __launch_bounds__(256) void colred_kernel(const T *a, T *b, T *X, T *R, int64_t n, int m,
                                                      int64_t rows_per, const double *coef,
-                                                     double *partial) {
+                                                     double *partial, double *X64) {
   __shared__ double red[256];
   const int cw = blockDim.x, ry = blockDim.y;
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -54,7 +55,8 @@ __global__ __launch_bounds__(256) void colred_kernel(const T *a, T *b, T *X, T *
           s += (double)p * (double)w;
         } else {
           const T p = a[e], w = b[e];
-          X[e] += (T)cf * p;
+          if constexpr (OP == 3) X64[e] += cf * (double)p;
+          else X[e] += (T)cf * p;
           const T rr = R[e] - (T)cf * w;
           R[e] = rr;
           s += (double)rr * (double)rr;
@@ -99,15 +101,17 @@ __global__ void colfinal_kernel(const double *partial, int nb, int m, int mode, 
 
 template <class T>
 int32_t colred(int op, const T *a, T *b, T *X, T *R, int64_t n, int m, const double *coef,
-               double *partial, hipStream_t s) {
+               double *partial, hipStream_t s, double *X64) {
   const ColRedShape sh = colred_shape(n, m);
   dim3 block(sh.cw, sh.ry), grid(sh.nb);
   if (op == 0)
-    hipLaunchKernelGGL((colred_kernel<T, 0>), grid, block, 0, s, a, b, X, R, n, m, sh.rows_per, coef, partial);
+    hipLaunchKernelGGL((colred_kernel<T, 0>), grid, block, 0, s, a, b, X, R, n, m, sh.rows_per, coef, partial, X64);
   else if (op == 1)
-    hipLaunchKernelGGL((colred_kernel<T, 1>), grid, block, 0, s, a, b, X, R, n, m, sh.rows_per, coef, partial);
+    hipLaunchKernelGGL((colred_kernel<T, 1>), grid, block, 0, s, a, b, X, R, n, m, sh.rows_per, coef, partial, X64);
+  else if (op == 2)
+    hipLaunchKernelGGL((colred_kernel<T, 2>), grid, block, 0, s, a, b, X, R, n, m, sh.rows_per, coef, partial, X64);
   else
-    hipLaunchKernelGGL((colred_kernel<T, 2>), grid, block, 0, s, a, b, X, R, n, m, sh.rows_per, coef, partial);
+    hipLaunchKernelGGL((colred_kernel<T, 3>), grid, block, 0, s, a, b, X, R, n, m, sh.rows_per, coef, partial, X64);
   NYS_LAUNCH_CHECK();
   return NYS_OK;
 }
@@ -122,9 +126,9 @@ int32_t colfinal(const double *partial, int64_t n, int m, int mode, double *out,
 }
 
 template int32_t colred<float>(int, const float *, float *, float *, float *, int64_t, int, const double *,
-                               double *, hipStream_t);
+                               double *, hipStream_t, double *);
 template int32_t colred<double>(int, const double *, double *, double *, double *, int64_t, int,
-                                const double *, double *, hipStream_t);
+                                const double *, double *, hipStream_t, double *);
 
 // ------------------------------------------------------------ elementwise
 // P = Z + beta P
@@ -248,6 +252,22 @@ int32_t gather_cols(const T *src, int m_old, const int *keep, int m_new, T *dst,
 template int32_t gather_cols<float>(const float *, int, const int *, int, float *, int64_t, hipStream_t);
 template int32_t gather_cols<double>(const double *, int, const int *, int, double *, int64_t, hipStream_t);
 
+__global__ void scatter_cols_d2f_kernel(const double *src, int ns, const int *idx, float *dst, int m, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * ns) return;
+  const int64_t i = e / ns;
+  const int k = (int)(e - i * ns);
+  dst[i * m + idx[k]] = (float)src[e];
+}
+int32_t scatter_cols_d2f(const double *src, int ns, const int *idx, float *dst, int m, int64_t n, hipStream_t s) {
+  if (ns <= 0) return NYS_OK;
+  const int64_t tot = n * ns;
+  hipLaunchKernelGGL(scatter_cols_d2f_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, src, ns, idx, dst,
+                     m, n);
+  NYS_LAUNCH_CHECK();
+  return NYS_OK;
+}
+
 // ------------------------------------------------------------ preconditioner apply
 // Z = U (gamma .* (U^T R)) + R / lambda_c with gamma_ic = -lh_i / (lambda_c (lh_i + lambda_c)),
 // the cancellation-free form of (lh_i + lambda_c)^{-1} - lambda_c^{-1}.
@@ -265,38 +285,51 @@ __global__ void gamma_scale_kernel(T *W, int r, int m, const double *lam_hat, co
 }
 
 size_t precond_apply_scratch_bytes(int64_t n, int r, int m, int prec) {
-  const size_t eb = prec == NYS_FP64 ? 8 : 4;
+  (void)prec;
   const int splits = gemm_tn_splits(n, r, m);
   Arena a;
-  a.take<char>((size_t)r * m * eb);
-  a.take<char>((size_t)splits * r * m * eb);
+  a.take<double>((size_t)r * m);
+  a.take<double>((size_t)splits * r * m);
   a.take<double>((size_t)m);
   return a.off;
 }
 
+// The arithmetic is float64 for every vector type: with lambda far below the
+// largest retained eigenvalue, the two terms of the closed form cancel in
+// span(U), and in float32 that cancellation leaves errors of about
+// u * lam_hat_1 / lambda relative to the smallest eigenvalue of P^{-1}, enough to
+// make the applied operator indefinite.  Float32 vectors are only rounded once,
+// on output (a relative perturbation, which keeps P^{-1} positive definite).
 template <class T>
 int32_t precond_apply_impl(const nys_precond &P, const double *lambdas, const T *R, int m, T *Z,
                            Arena &ws, hipStream_t s) {
   const int64_t n = P.n;
   const int r = P.r;
   const int splits = gemm_tn_splits(n, r, m);
-  T *W = ws.take<T>((size_t)r * m);
-  T *part = ws.take<T>((size_t)splits * r * m);
+  double *W = ws.take<double>((size_t)r * m);
+  double *part = ws.take<double>((size_t)splits * r * m);
   double *inv_lam = ws.take<double>((size_t)m);
   if (ws.overflowed()) {
     set_error("precond apply: workspace too small");
     return NYS_ENOMEM;
   }
   if (ws.measuring()) return NYS_OK;
-  const T *U;
-  if constexpr (sizeof(T) == 8) U = reinterpret_cast<const T *>(P.U);
-  else U = reinterpret_cast<const T *>(P.U32);
-  NYS_RETURN_IF(gemm_tn<T>(U, r, R, m, n, r, m, W, m, part, splits, s));
+  const double *U = P.U;
+  if constexpr (sizeof(T) == 8) {
+    NYS_RETURN_IF(gemm_tn<double>(U, r, reinterpret_cast<const double *>(R), m, n, r, m, W, m, part, splits, s));
+  } else {
+    NYS_RETURN_IF(gemm_tn_df(U, r, reinterpret_cast<const float *>(R), m, n, r, m, W, m, part, splits, s));
+  }
   const int64_t tot = std::max<int64_t>((int64_t)r * m, m);
-  hipLaunchKernelGGL(gamma_scale_kernel<T>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, W, r, m,
+  hipLaunchKernelGGL(gamma_scale_kernel<double>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, W, r, m,
                      P.lam_hat, lambdas, inv_lam);
   NYS_LAUNCH_CHECK();
-  return gemm_nn<T>(U, r, W, m, n, r, m, Z, m, 1, R, m, inv_lam, s);
+  if constexpr (sizeof(T) == 8)
+    return gemm_nn<double>(U, r, W, m, n, r, m, reinterpret_cast<double *>(Z), m, 1,
+                           reinterpret_cast<const double *>(R), m, inv_lam, s);
+  else
+    return gemm_nn_dd_f(U, r, W, m, n, r, m, reinterpret_cast<float *>(Z), m,
+                        reinterpret_cast<const float *>(R), m, inv_lam, s);
 }
 
 template int32_t precond_apply_impl<float>(const nys_precond &, const double *, const float *, int, float *,

@@ -89,7 +89,7 @@ def test_solve_argument_errors(lib):
     assert solve([-1.0]) == nys.EINVAL
     assert solve([float("nan")]) == nys.EINVAL
     assert solve([1.0], tol=0.0) == nys.EINVAL
-    assert solve([1.0], prec=3) == nys.EINVAL
+    assert solve([1.0], prec=4) == nys.EINVAL
     assert solve([1.0], mode=2) == nys.EINVAL
     assert solve([1.0], max_iters=-1) == nys.EINVAL
     assert solve([1.0], nrhs=0) == nys.EINVAL
@@ -106,11 +106,16 @@ def test_sketch_and_build_argument_errors(lib):
     assert lib.nys_precond_build(FAKE, FAKE, 10, 3, 0, ctypes.byref(P2), FAKE, 0, None) == nys.EINVAL
 
 
-def test_precond_apply_requires_fp32_copy(lib):
+def test_precond_apply_argument_errors(lib):
     P = nys.NysPrecondC(10, 3, 3, FAKE, None, FAKE, 0.0)
-    assert lib.nys_precond_apply(ctypes.byref(P), FAKE, nys.FP32, FAKE, 1, ctypes.c_void_p(8192), FAKE, 1 << 20,
-                                 None) == nys.EINVAL
+    other = ctypes.c_void_p(8192)
+    # R and Z aliasing, no columns, missing lambdas, unknown precision: rejected before any device work
     assert lib.nys_precond_apply(ctypes.byref(P), FAKE, nys.FP64, FAKE, 1, FAKE, FAKE, 1 << 20, None) == nys.EINVAL
+    assert lib.nys_precond_apply(ctypes.byref(P), FAKE, nys.FP32, FAKE, 0, other, FAKE, 1 << 20, None) == nys.EINVAL
+    assert lib.nys_precond_apply(ctypes.byref(P), None, nys.FP32, FAKE, 1, other, FAKE, 1 << 20, None) == nys.EINVAL
+    assert lib.nys_precond_apply(ctypes.byref(P), FAKE, 7, FAKE, 1, other, FAKE, 1 << 20, None) == nys.EINVAL
+    bad = nys.NysPrecondC(10, 0, 0, FAKE, None, FAKE, 0.0)
+    assert lib.nys_precond_apply(ctypes.byref(bad), FAKE, nys.FP64, FAKE, 1, other, FAKE, 1 << 20, None) == nys.EINVAL
 
 
 def test_tile_sources_avoid_packed_fp32_ops():

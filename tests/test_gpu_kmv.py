@@ -21,7 +21,7 @@ import oracle as o
 
 pytestmark = pytest.mark.gpu
 
-U = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -16}
+U = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -16, 3: 2.0 ** -16}
 
 
 def bound(Xr, Xc, V, kind, sigma, prec, deriv=0):
@@ -75,7 +75,7 @@ def check(nys, n_r, n_c, d, m, kind, prec, seed=0, same=True, deriv=0, heavy=Fal
     return got, ref
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("n,d,m", [(1, 3, 1), (31, 10, 1), (257, 16, 3), (2000, 10, 1), (700, 20, 8),
                                    (513, 33, 16), (300, 1, 5)])
@@ -83,7 +83,7 @@ def test_matvec_small_m(nys, prec, kind, n, d, m):
     check(nys, n, n, d, m, kind, prec, seed=n + d + m)
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("n,d,m", [(100, 10, 17), (1000, 16, 64), (777, 20, 50), (1500, 32, 200),
                                    (2000, 10, 300)])
@@ -156,11 +156,11 @@ def test_matvec_large_sampled_rows(nys):
     tX = torch.from_numpy(X).to(dev)
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(X.shape[0], 24, replace=False))
-    for m in (1, 512):
+    for m, prec in ((1, 2), (512, 2), (512, 3)):
         V = rng.standard_normal((X.shape[0], m)).astype(np.float32)
         tV = torch.from_numpy(V).to(dev)
-        print(f"case n=1e6 d=16 m={m} bf16x3", flush=True)
-        out = nys.kernel_matvec(tX, tX, tV, o.RBF, w.sigma, 2)
+        print(f"case n=1e6 d=16 m={m} prec={prec}", flush=True)
+        out = nys.kernel_matvec(tX, tX, tV, o.RBF, w.sigma, prec)
         torch.cuda.synchronize()
         got = out[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
         ref = o.kernel_matvec_rows(X[rows], X, V.astype(np.float64), o.RBF, w.sigma)
@@ -171,3 +171,21 @@ def test_matvec_large_sampled_rows(nys):
         tol = (16 * 2.0 ** -16 * (1 + kap * span) + (X.shape[0] / 4 + 16) * 2.0 ** -24) * Kabs
         assert np.max(np.abs(got - ref) / tol) <= 1.0
         del out, tV
+
+
+def test_six_term_distance_is_more_accurate(nys):
+    """BF16X3_D6 splits the distance operands into three bf16 parts.  Products with
+    unit vectors return single kernel entries (no accumulation error), so the
+    entry error of the two splits can be compared directly: about 2^-16 relative
+    for three terms, float32 level for six."""
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((3000, 16))
+    J = rng.choice(3000, 16, replace=False)
+    V = np.zeros((3000, 16))
+    V[J, np.arange(16)] = 1.0
+    ref = o.kernel_matrix(X, X, o.RBF, 4.0)[:, J]
+    e3 = np.max(np.abs(run(nys, X, X, V, o.RBF, 4.0, 2) - ref) / ref)
+    e6 = np.max(np.abs(run(nys, X, X, V, o.RBF, 4.0, 3) - ref) / ref)
+    print(f"max relative entry error: 3-term {e3:.3e}, 6-term {e6:.3e}")
+    assert e3 < 2.0 ** -11
+    assert e6 < e3 / 16 and e6 < 2.0 ** -18
