@@ -270,8 +270,13 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       if (ov.tm) p.tm = ov.tm;
       if (ov.r) p.r = ov.r;
     }
+    // BF16X3 chunks of >= 64 columns run on the pipelined eight-wave tile
+    if (prec == NYS_BF16X3 && p.tm >= 64 && p.r == 2) p.waves = 8;
   }
-  const int TI = 4 * p.r * 16;
+  if (p.path == 0 || p.waves != 8) {
+    p.waves = 4;
+  }
+  const int TI = p.waves * p.r * 16;
   const int TJ = p.path == 0 ? 64 : 32;
   const int64_t ntiles = ceil_div(nr, TI);
   const int chunks = p.path == 0 ? 1 : (int)ceil_div(m, p.tm);
@@ -357,7 +362,7 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, c
     a.cL = prec == NYS_FP64 ? 1.0 / k.sigma : log2e / k.sigma;
     a.dcoef = 1.0 / (k.sigma * k.sigma);
   }
-  const int TI = 4 * plan.r * 16;
+  const int TI = plan.waves * plan.r * 16;
   const int64_t ntiles = ceil_div(rows.n, TI);
   int chunks = 1;
   if (plan.path == 1) {

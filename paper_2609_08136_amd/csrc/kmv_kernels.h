@@ -364,6 +364,206 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_flash_kernel(KArgs a) {
       }
 }
 
+// ===================================================================== flash, pipelined (BF16X3)
+// Eight waves (256 rows, 32 per wave) share one TM-column chunk of the split V.
+// Column tiles of TJ = 32 points are double buffered in LDS: while the MFMAs
+// consume tile t, the split V of tile t+1 streams into the other buffer by direct
+// global-to-LDS loads (no registers) and the packed points of tile t+1 wait in
+// registers; one barrier per tile.  Per tile and wave: 2 R KS MFMAs for the
+// exponents, 3 R TM/16 for K V.
+constexpr int KMV2_THREADS = 512;
+
+template <int KIND, int KSMAX, int TM>
+__global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
+  using T = Tr<NYS_BF16X3>;
+  using Op = typename T::Op;
+  constexpr int R = 2, WAVES = KMV2_THREADS / 64;
+  constexpr int TJ = 32, TI = WAVES * R * 16, NCB = TM / 16;
+  constexpr int VCH = TM * 4;                      // 16-byte chunks per V part per tile
+  typedef __attribute__((address_space(3))) void lds_void;
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int strideA = lds_stride<NYS_BF16X3>(a.Kp);
+  const size_t a_bytes = ((size_t)TJ * strideA * 2 + 15) & ~size_t(15);
+  u16 *const sA0 = reinterpret_cast<u16 *>(smem);
+  u16 *const sA1 = reinterpret_cast<u16 *>(smem + a_bytes);
+  u16 *const sV0 = reinterpret_cast<u16 *>(smem + 2 * a_bytes);
+  u16 *const sV1 = sV0 + 2 * TM * 32;
+
+  const int64_t ntiles = (a.nr + TI - 1) / TI;
+  const int64_t nb = ntiles * a.chunks * a.nsplit;
+  const int64_t nb_pad = (nb + 7) / 8 * 8;
+  const int64_t lid = xcd_logical_block(nb_pad);
+  if (lid >= nb) return;
+  const int64_t tile = lid % ntiles;
+  const int64_t rest = lid / ntiles;
+  const int chunk = (int)(rest % a.chunks);
+  const int split = (int)(rest / a.chunks);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col16 = lane & 15, grp = lane >> 4;
+  const int ks = a.Kp / T::KSTEP;
+  const int64_t i0 = tile * TI;
+  const int64_t iw = i0 + (int64_t)wave * R * 16;
+  const int c0 = chunk * TM;
+  const u16 *Ag = reinterpret_cast<const u16 *>(a.Acols);
+  const u16 *Bg = reinterpret_cast<const u16 *>(a.Brows);
+  const u16 *Vh = reinterpret_cast<const u16 *>(a.V);
+  const u16 *Vl = reinterpret_cast<const u16 *>(a.V2);
+
+  Op bop[R][KSMAX];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+      bop[r][s] = (s < ks) ? load_op<NYS_BF16X3>(Bg + (iw + r * 16 + col16) * a.Kp + s * T::KSTEP + grp * T::KL)
+                           : zero_op<NYS_BF16X3>();
+
+  f4 acc[R][NCB];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = f4{0, 0, 0, 0};
+
+  const float cL = (float)a.cL, dcoef = (float)a.dcoef;
+  const int64_t njt = (a.nc + TJ - 1) / TJ;
+  const int64_t jt0 = (int64_t)split * a.jsteps;
+  const int64_t jt1 = jt0 + a.jsteps < njt ? jt0 + a.jsteps : njt;
+
+  // packed points of one tile: TJ rows x Kp bf16 = TJ * Kp / 8 chunks (<= KSMAX * 128)
+  constexpr int APRE = (KSMAX * 128 + KMV2_THREADS - 1) / KMV2_THREADS;
+  const int cpr = a.Kp / 8;
+  const int achunks = TJ * cpr;
+  uint4 apre[APRE];
+  auto load_points = [&](int64_t jt) {
+    const uint4 *g = reinterpret_cast<const uint4 *>(Ag + jt * TJ * a.Kp);
+#pragma unroll
+    for (int k = 0; k < APRE; ++k) {
+      const int c = tid + k * KMV2_THREADS;
+      if (c < achunks) apre[k] = g[c];
+    }
+  };
+  auto store_points = [&](u16 *dst) {
+#pragma unroll
+    for (int k = 0; k < APRE; ++k) {
+      const int c = tid + k * KMV2_THREADS;
+      if (c < achunks) {
+        const int r = c / cpr, o = c - r * cpr;
+        *reinterpret_cast<uint4 *>(dst + r * strideA + o * 8) = apre[k];
+      }
+    }
+  };
+  // split V of one tile: two contiguous runs of TM*32 bf16, copied by the waves in
+  // 1 KB blocks (lane L of the wave lands 16 L bytes into the block)
+  auto stream_v = [&](int64_t jt, u16 *dst) {
+    const u16 *gh = Vh + (jt * a.m_pad + c0) * 32;
+    const u16 *gl = Vl + (jt * a.m_pad + c0) * 32;
+#pragma unroll
+    for (int k = 0; k < (VCH + KMV2_THREADS - 1) / KMV2_THREADS; ++k) {
+      const int blk = k * KMV2_THREADS + wave * 64;          // wave-uniform
+      if (blk < VCH) {
+        const int q = blk + lane;
+        __builtin_amdgcn_global_load_lds(gh + q * 8, (lds_void *)(dst + blk * 8), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(gl + q * 8, (lds_void *)(dst + TM * 32 + blk * 8), 16, 0, 0);
+      }
+    }
+  };
+
+  if (jt0 < jt1) {
+    load_points(jt0);
+    stream_v(jt0, sV0);
+    store_points(sA0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  for (int64_t jt = jt0; jt < jt1; ++jt) {
+    const int cur = (int)((jt - jt0) & 1);
+    const u16 *sAc = cur ? sA1 : sA0;
+    const u16 *sVh = cur ? sV1 : sV0;
+    const u16 *sVl = sVh + TM * 32;
+    const bool more = jt + 1 < jt1;
+    if (more) {
+      stream_v(jt + 1, cur ? sV0 : sV1);
+      load_points(jt + 1);
+    }
+    const int64_t j0 = jt * TJ;
+    const bool diag = a.same && (j0 < i0 + TI) && (i0 < j0 + TJ);
+
+    Op aopA[KSMAX], aopB[KSMAX];
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) {
+      aopA[s] = (s < ks) ? load_op<NYS_BF16X3>(sAc + col16 * strideA + s * T::KSTEP + grp * T::KL)
+                         : zero_op<NYS_BF16X3>();
+      aopB[s] = (s < ks) ? load_op<NYS_BF16X3>(sAc + (16 + col16) * strideA + s * T::KSTEP + grp * T::KL)
+                         : zero_op<NYS_BF16X3>();
+    }
+    bf8 phi[R], plo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      f4 ta = {0, 0, 0, 0}, tb = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s)
+        if (s < ks) {
+          ta = mfma16(aopA[s], bop[r][s], ta);
+          tb = mfma16(aopB[s], bop[r][s], tb);
+        }
+      const int64_t gi = iw + r * 16 + col16;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float t = e < 4 ? ta[e] : tb[e - 4];
+        const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
+        if (diag && gi == gj) t = 0.0f;
+        const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);
+        const __bf16 h = (__bf16)kv;
+        phi[r][e] = h;
+        plo[r][e] = (__bf16)(kv - (float)h);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const bf8 vh = *reinterpret_cast<const bf8 *>(sVh + (cb * 16 + col16) * 32 + grp * 8);
+      const bf8 vl = *reinterpret_cast<const bf8 *>(sVl + (cb * 16 + col16) * 32 + grp * 8);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc[r][cb] = mfma16(phi[r], vh, acc[r][cb]);
+        acc[r][cb] = mfma16(phi[r], vl, acc[r][cb]);
+        acc[r][cb] = mfma16(plo[r], vh, acc[r][cb]);
+      }
+    }
+    if (more) store_points(cur ? sA0 : sA1);
+    __builtin_amdgcn_s_waitcnt(0);   // the streamed tile has landed
+    __syncthreads();
+  }
+
+  float *O = reinterpret_cast<float *>(a.Out);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = iw + r * 16 + out_row<NYS_BF16X3>(grp, v);
+        const int c = c0 + cb * 16 + col16;
+        if (i < a.nr && c < a.m) {
+          const float sum = acc[r][cb][v];
+          if (a.partial) {
+            O[((int64_t)split * a.nr + i) * a.m + c] = sum;
+          } else {
+            float val = (float)a.alpha * sum;
+            if (a.beta != 0.0) val += (float)a.beta * O[i * a.ldo + c];
+            O[i * a.ldo + c] = val;
+          }
+        }
+      }
+}
+
+template <int TM>
+inline size_t kmv_flash2_lds(int Kp) {
+  const size_t a = ((size_t)32 * lds_stride<NYS_BF16X3>(Kp) * 2 + 15) & ~size_t(15);
+  return 2 * a + (size_t)2 * 2 * TM * 32 * 2;
+}
+
 // LDS bytes of the kernels above for a given plan.
 template <int PREC>
 inline size_t kmv_small_lds(int Kp, int MM) {

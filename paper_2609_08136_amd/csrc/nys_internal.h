@@ -106,6 +106,7 @@ struct KmvPlan {
   int mm = 1;            // small path: compile-time column bound
   int tm = 64;           // flash path: column chunk
   int r = 4;             // row subtiles of 16 per wave
+  int waves = 4;         // waves per workgroup (8: pipelined BF16X3 flash tile)
   int splits = 1;        // split of the column (j) range
   int jsteps = 0;        // j tiles per split
   int64_t m_pad = 0;     // flash BF16: padded width of the split V

@@ -213,7 +213,15 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
       }
       // cycle target: delta times the residual the cycle started from (may lie
       // below tol: acceptance is on the true residual), or tol without cycles
-      thr[q] = c.delta > 0.0 ? std::max(1e-3 * tol, c.delta * c.rstart) : tol;
+      // The last cycle aims at 0.3 tol (the true residual ends a little above the
+      // recursive one); a cycle whose target is within 10x of that becomes the last.
+      if (c.delta > 0.0) {
+        const double last = 0.3 * tol;
+        thr[q] = c.delta * c.rstart;
+        if (thr[q] < 10.0 * last) thr[q] = last;
+      } else {
+        thr[q] = tol;
+      }
       // a recursion whose residual grew 10x above its best of the cycle has lost
       // its footing: refine (and restart) it now
       const bool diverging = refine && rel[q] > 10.0 * c.rmin && rel[q] > tol;
