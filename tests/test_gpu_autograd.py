@@ -1,0 +1,99 @@
+"""Differentiation through the NysPCG solution (autograd wrappers over the C ABI):
+gradients of the validation loss with respect to (log lambda, log sigma) against
+the oracle's dense float64 gradient and against central differences, and a short
+gradient descent on the differentiation workload's n = 3000 subsample."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import nys_inputs as ni
+import oracle as o
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, torch.float64)
+
+
+@pytest.fixture(scope="module")
+def subsample():
+    w = ni.differentiation(0)            # 1e5 train + 2e4 validation rows, d = 16, Laplacian
+    X, y = w.X[:3000], w.B[:3000, 0]
+    Xv, yv = w.Xval[:600], w.yval[:600]
+    lam0 = 1e-3 * 3000                   # lambda / n as in the full workload
+    return X, y, Xv, yv, lam0, w.sigma, w.kind
+
+
+def loss_and_grad(nys, ag, X, y, Xv, yv, lam, sig, kind, r=200, seed=0):
+    tX, ty, tXv, tyv = T(X), T(y), T(Xv), T(yv)
+    P = nys.build_preconditioner(tX, T(ni.gaussian_test_matrix(len(X), r, seed)), kind, sig, nys.FP64)
+    tl = torch.tensor(math.log(lam), dtype=torch.float64, device=DEV, requires_grad=True)
+    ts = torch.tensor(math.log(sig), dtype=torch.float64, device=DEV, requires_grad=True)
+    L = ag.validation_loss(tX, ty, tXv, tyv, tl, ts, kind, P, dict(tol=1e-12, prec=nys.FP64))
+    L.backward()
+    return float(L), float(tl.grad), float(ts.grad)
+
+
+def test_gradient_matches_dense_oracle_and_differences(nys, subsample):
+    from paper_2609_08136_amd import autograd as ag
+    X, y, Xv, yv, lam, sig, kind = subsample
+    L, gl, gs = loss_and_grad(nys, ag, X, y, Xv, yv, lam, sig, kind)
+    Lo, dlam, dsig, _, _ = o.validation_loss_grad(X, y, Xv, yv, kind, sig, lam)
+    print(f"L {L:.12e} vs {Lo:.12e}; dL/dlog lambda {gl:.10e} vs {lam * dlam:.10e}; "
+          f"dL/dlog sigma {gs:.10e} vs {sig * dsig:.10e}")
+    assert L == pytest.approx(Lo, rel=1e-9)
+    assert gl == pytest.approx(lam * dlam, rel=1e-7)
+    assert gs == pytest.approx(sig * dsig, rel=1e-7)
+    # central differences of the GPU loss itself, h = 1e-4 on the log parameters
+    h = 1e-4
+    f = lambda a, b: loss_and_grad(nys, ag, X, y, Xv, yv, math.exp(a), math.exp(b), kind)[0]
+    la, ls = math.log(lam), math.log(sig)
+    fd_l = (f(la + h, ls) - f(la - h, ls)) / (2 * h)
+    fd_s = (f(la, ls + h) - f(la, ls - h)) / (2 * h)
+    print(f"central differences: {fd_l:.10e} {fd_s:.10e}")
+    assert gl == pytest.approx(fd_l, rel=1e-5)
+    assert gs == pytest.approx(fd_s, rel=1e-5)
+
+
+def test_kernel_product_backward_matches_oracle(nys):
+    from paper_2609_08136_amd import autograd as ag
+    rng = np.random.default_rng(3)
+    Xr, Xc = rng.standard_normal((70, 5)), rng.standard_normal((90, 5))
+    v, g = rng.standard_normal(90), rng.standard_normal(70)
+    tv = T(v).requires_grad_(True)
+    ts = torch.tensor(1.7, dtype=torch.float64, device=DEV, requires_grad=True)
+    out = ag.KernelProduct.apply(T(Xr), T(Xc), tv, ts, o.RBF)
+    out.backward(T(g))
+    K = o.kernel_matrix(Xr, Xc, o.RBF, 1.7)
+    dK = o.kernel_dsigma_matrix(Xr, Xc, o.RBF, 1.7)
+    assert np.allclose(out.detach().cpu().numpy(), K @ v, rtol=1e-12, atol=1e-12)
+    assert np.allclose(tv.grad.cpu().numpy(), K.T @ g, rtol=1e-12, atol=1e-12)
+    assert float(ts.grad) == pytest.approx(float(g @ (dK @ v)), rel=1e-11)
+
+
+def test_gradient_descent_decreases_validation_loss(nys, subsample):
+    """20 steps of gradient descent on (log lambda, log sigma), step 0.05, halved when
+    the loss would increase; the loss must decrease monotonically."""
+    from paper_2609_08136_amd import autograd as ag
+    X, y, Xv, yv, lam, sig, kind = subsample
+    theta = np.array([math.log(lam), math.log(sig)])
+    eta = 0.05
+    L, gl, gs = loss_and_grad(nys, ag, X, y, Xv, yv, lam, sig, kind, r=100)
+    hist = [L]
+    for step in range(20):
+        g = np.array([gl, gs])
+        while True:
+            cand = theta - eta * g
+            Lc, glc, gsc = loss_and_grad(nys, ag, X, y, Xv, yv, math.exp(cand[0]), math.exp(cand[1]), kind, r=100)
+            if Lc <= L or eta < 1e-6:
+                break
+            eta *= 0.5
+        theta, L, gl, gs = cand, Lc, glc, gsc
+        hist.append(L)
+    print("validation loss:", " ".join(f"{v:.6f}" for v in hist), "eta", eta)
+    assert all(b <= a for a, b in zip(hist, hist[1:]))
+    assert hist[-1] < hist[0]
