@@ -49,7 +49,152 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kmv-only", action="store_true", help="time the kernel product only (profiling)")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--workload", default="batched_lambda_grid",
+                    choices=["batched_lambda_grid", "plain_fp64", "matrix_free_fp32", "precision_variant",
+                             "differentiation"],
+                    help="batched_lambda_grid is the headline workload; the others are recorded separately")
     return ap.parse_args()
+
+
+# ----------------------------------------------------------------------------- other workloads
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fn()
+    torch.cuda.synchronize()
+    return res, time.perf_counter() - t0
+
+
+def _solve_once(nys, torch, X, B, w, Om0, prec, sketch_prec, **opts):
+    """sketch + build + solve; returns (Xsol, info, rc, P, seconds)."""
+    Om = Om0.clone()
+    def run():
+        P = nys.build_preconditioner(X, Om, w.kind, w.sigma, sketch_prec)
+        x, info, rc = nys.nyspcg_solve(X, B, w.lambdas, w.kind, w.sigma, P, tol=w.tol, prec=prec, **opts)
+        return x, info, rc, P
+    (x, info, rc, P), t = _timed(torch, run)
+    return x, info, rc, P, t
+
+
+def run_other(args):
+    import numpy as np
+    import torch
+
+    import nys_inputs as ni
+    import oracle as o
+    import paper_2609_08136_amd as nys
+
+    nys.load()
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    wl = args.workload
+    out = {"n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic", "unit": "s", "device": torch.cuda.get_device_name(0)}
+
+    if wl == "plain_fp64":
+        w = ni.plain_fp64(args.seed)
+        X, B, Om0 = T(w.X), T(w.B), T(ni.gaussian_test_matrix(w.n, w.r, args.seed))
+        _solve_once(nys, torch, X, B, w, Om0, nys.FP64, nys.FP64, max_iters=10)          # warmup
+        x, info, rc, P, t = _solve_once(nys, torch, X, B, w, Om0, nys.FP64, nys.FP64, check_true=True)
+        K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+        ref = o.direct_solve(K, w.B[:, 0], w.lambdas[0])
+        xs = x.cpu().numpy().reshape(-1)
+        t0 = time.perf_counter()
+        o.nyspcg_dense(w.X, w.B, w.lambdas, w.kind, w.sigma, ni.gaussian_test_matrix(w.n, w.r, args.seed), tol=w.tol)
+        t_cpu = time.perf_counter() - t0
+        out.update(metric="NysPCG time-to-1e-8 rel. residual, n=2000 d=10, FP64", value=round(t, 5),
+                   ms_per_step=round(t * 1e3, 3), dtype="f64",
+                   config={"workload": "plain_fp64", "n": w.n, "d": w.d, "rank": w.r, "lambda": w.lambdas[0],
+                           "sigma": w.sigma, "tol": w.tol},
+                   solve={"status": rc, "iters": info[0]["iters"], "relres_true": info[0]["relres_true"],
+                          "rel_error_vs_cholesky": float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))},
+                   cpu_baseline={"value": t_cpu, "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
+                                 "sample": "the whole workload: dense K, Nystrom, textbook PCG (float64 NumPy)"})
+    elif wl == "matrix_free_fp32":
+        w = ni.matrix_free_fp32(args.seed)
+        X, B = T(w.X), T(w.B)
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed + ni.OMEGA_SEED_OFFSET)
+        Om0 = torch.randn((w.n, w.r), generator=g, device=dev, dtype=torch.float64)
+        _solve_once(nys, torch, X, B, w, Om0, nys.FP32, nys.FP32, max_iters=10, refine_every=0)
+        x, info, rc, P, t = _solve_once(nys, torch, X, B, w, Om0, nys.FP32, nys.FP32, refine_every=0,
+                                        refine_mode=1)
+        x2, info2, rc2, _, t2 = _solve_once(nys, torch, X, B, w, Om0, nys.FP32, nys.FP32, refine_every=-1,
+                                            check_true=True)
+        V = torch.randn((w.n, 1), generator=g, device=dev, dtype=torch.float32)
+        nys.kernel_matvec(X, X, V, w.kind, w.sigma, nys.FP32)
+        _, tk = _timed(torch, lambda: nys.kernel_matvec(X, X, V, w.kind, w.sigma, nys.FP32))
+        out.update(metric="NysPCG time-to-1e-6 float64 rel. residual, n=2e5 d=20, FP32 matrix-free",
+                   value=round(t, 3), ms_per_step=round(t * 1e3, 1), dtype="f32",
+                   config={"workload": "matrix_free_fp32", "n": w.n, "d": w.d, "rank": w.r,
+                           "lambda": w.lambdas[0], "sigma": w.sigma, "tol": w.tol},
+                   solve={"status": rc, "iters": info[0]["iters"], "refinements": info[0]["refinements"],
+                          "relres_true": info[0]["relres_true"]},
+                   without_refinement={"seconds": round(t2, 3), "status": rc2, "iters": info2[0]["iters"],
+                                       "relres_recursive": info2[0]["relres_recursive"],
+                                       "relres_true": info2[0]["relres_true"]},
+                   kernel_matvec_m1_ms=round(tk * 1e3, 3))
+    elif wl == "precision_variant":
+        w = ni.precision_variant(args.seed)
+        X, B = T(w.X), T(w.B)
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed + ni.OMEGA_SEED_OFFSET)
+        Om0 = torch.randn((w.n, w.r), generator=g, device=dev, dtype=torch.float64)
+        res = {}
+        for name, prec in (("bf16x3", nys.BF16X3), ("fp32", nys.FP32)):
+            _solve_once(nys, torch, X, B, w, Om0, prec, prec, max_iters=10, refine_every=20)
+            x, info, rc, P, t = _solve_once(nys, torch, X, B, w, Om0, prec, prec, refine_every=20, refine_mode=1)
+            res[name] = {"seconds": round(t, 3), "status": rc, "iters": info[0]["iters"],
+                         "refinements": info[0]["refinements"], "relres_true": info[0]["relres_true"]}
+            if args.verbose:
+                print(name, res[name], file=sys.stderr, flush=True)
+        out.update(metric="NysPCG time-to-1e-6 float64 rel. residual, n=5e5 d=32, BF16X3 + FP64 refinement",
+                   value=res["bf16x3"]["seconds"], ms_per_step=round(res["bf16x3"]["seconds"] * 1e3, 1),
+                   dtype="bf16x3",
+                   config={"workload": "precision_variant", "n": w.n, "d": w.d, "rank": w.r,
+                           "lambda": w.lambdas[0], "sigma": w.sigma, "tol": w.tol, "refine_every": 20},
+                   runs=res, speedup_vs_fp32=round(res["fp32"]["seconds"] / res["bf16x3"]["seconds"], 3))
+    else:  # differentiation
+        from paper_2609_08136_amd import autograd as ag
+        w = ni.differentiation(args.seed)
+        X, y, Xv, yv = T(w.X), T(w.B[:, 0]), T(w.Xval), T(w.yval)
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed + ni.OMEGA_SEED_OFFSET)
+        Om0 = torch.randn((w.n, w.r), generator=g, device=dev, dtype=torch.float64)
+        opts = dict(tol=1e-10, prec=nys.FP64)
+
+        def loss_grad(theta):
+            P = nys.build_preconditioner(X, Om0.clone(), w.kind, math.exp(theta[1]), nys.FP64)
+            tl = torch.tensor(theta[0], dtype=torch.float64, device=dev, requires_grad=True)
+            ts = torch.tensor(theta[1], dtype=torch.float64, device=dev, requires_grad=True)
+            L = ag.validation_loss(X, y, Xv, yv, tl, ts, w.kind, P, opts)
+            L.backward()
+            return float(L), np.array([float(tl.grad), float(ts.grad)])
+
+        theta = np.array([math.log(w.lambdas[0]), math.log(w.sigma)])
+        loss_grad(theta)                                                              # warmup
+        (L, gr), t_one = _timed(torch, lambda: loss_grad(theta))
+        eta, hist = 0.05, [L]
+        t0 = time.perf_counter()
+        for _ in range(20):
+            while True:
+                cand = theta - eta * gr
+                Lc, gc = loss_grad(cand)
+                if Lc <= L or eta < 1e-6:
+                    break
+                eta *= 0.5
+            theta, L, gr = cand, Lc, gc
+            hist.append(L)
+        t_gd = time.perf_counter() - t0
+        out.update(metric="validation loss + adjoint gradient time, n=1e5 train / 2e4 val, d=16, Laplacian, FP64",
+                   value=round(t_one, 3), ms_per_step=round(t_one * 1e3, 1), dtype="f64",
+                   config={"workload": "differentiation", "n_train": w.n, "n_val": w.Xval.shape[0], "d": w.d,
+                           "rank": w.r, "lambda0": w.lambdas[0], "sigma0": w.sigma, "kernel": "laplacian"},
+                   gradient_descent={"steps": 20, "eta_final": eta, "seconds": round(t_gd, 2),
+                                     "loss": [round(v, 8) for v in hist],
+                                     "lambda": math.exp(theta[0]), "sigma": math.exp(theta[1])})
+    print(json.dumps(out))
 
 
 def log(args, *a):
@@ -125,6 +270,9 @@ def main():
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload != "batched_lambda_grid":
+        run_other(args)
+        return
 
     import numpy as np
     import torch
