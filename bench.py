@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kmv-only", action="store_true", help="time the kernel product only (profiling)")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--prec", default="bf16x3_d10", choices=["bf16x3", "bf16x3_d6", "bf16x3_d10"],
+                    help="kernel-product precision of the batched workload")
     ap.add_argument("--workload", default="batched_lambda_grid",
                     choices=["batched_lambda_grid", "plain_fp64", "matrix_free_fp32", "precision_variant",
                              "differentiation"],
@@ -288,7 +290,7 @@ def main():
     m = nrhs * nlam
     # the smallest lambda (1e-7 n) lies below the three-term distance error, so the
     # six-term distance split is needed for a positive-definite perturbed operator
-    prec = nys.BF16X3_D6
+    prec = nys.PREC_BY_NAME[args.prec]
     X = torch.from_numpy(w.X).to(dev)
     B = torch.from_numpy(w.B).to(dev)
     g = torch.Generator(device=dev)
@@ -378,7 +380,7 @@ def main():
             "workload": "batched_lambda_grid",
             "n": n, "d": d, "kernel": "rbf", "sigma": w.sigma, "nrhs": nrhs, "nlam": nlam,
             "lambdas": [float(v) for v in w.lambdas], "rank": r, "tol": w.tol,
-            "precision": "bf16x3 K V, fp32 CG, fp64 residual refinement",
+            "precision": f"{args.prec} K V, fp32 CG, fp64 residual refinement",
             "refine_every": args.refine_every, "refine_mode": args.refine_mode,
         },
         "kernel_matvec_tflops": round(kmv_tflops, 1),

@@ -44,6 +44,13 @@
  *                about 2^-17 (d / sigma^2) |K|; when lambda is below that the
  *                perturbed operator can be indefinite and CG diverges, so small
  *                regularisations (lambda < ~1e-5 |K|) need this variant.
+ *    NYS_BF16X3_D10 four bf16 parts per distance operand and the ten products
+ *                of total order <= 3 (hh; hm, mh; hl, lh, mm; h4, 4h, ml, lm),
+ *                about 32 bits.  The six-term split still leaves a structured
+ *                distance error of about 2^-27 (d / sigma^2) |K|, which bounds
+ *                how much one float64 refinement cycle can gain when lambda is
+ *                within a few decades of 1e-7 |K|; the ten-term split removes it
+ *                for about 1.5x the distance work (d <= 24).
  */
 #ifndef NYS_H
 #define NYS_H
@@ -67,7 +74,7 @@ extern "C" {
 #define NYS_ENOMEM        (-5) /* workspace smaller than nys_workspace_bytes() */
 
 typedef enum { NYS_RBF = 0, NYS_LAPLACIAN = 1 } nys_kind;
-typedef enum { NYS_FP64 = 0, NYS_FP32 = 1, NYS_BF16X3 = 2, NYS_BF16X3_D6 = 3 } nys_prec;
+typedef enum { NYS_FP64 = 0, NYS_FP32 = 1, NYS_BF16X3 = 2, NYS_BF16X3_D6 = 3, NYS_BF16X3_D10 = 4 } nys_prec;
 
 /* Operations whose workspace can be queried. */
 typedef enum {

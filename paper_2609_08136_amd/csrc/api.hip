@@ -29,8 +29,15 @@ int32_t einval(const std::string &m) {
   set_error(m);
   return NYS_EINVAL;
 }
-bool valid_prec(int p) { return p == NYS_FP64 || p == NYS_FP32 || p == NYS_BF16X3 || p == NYS_BF16X3_D6; }
-int max_dim(int prec) { return prec == NYS_BF16X3 ? 82 : (prec == NYS_BF16X3_D6 ? 41 : 62); }
+bool valid_prec(int p) { return p >= NYS_FP64 && p <= NYS_BF16X3_D10; }
+int max_dim(int prec) {
+  switch (prec) {
+    case NYS_BF16X3: return 82;
+    case NYS_BF16X3_D6: return 41;
+    case NYS_BF16X3_D10: return 24;
+    default: return 62;
+  }
+}
 size_t elem_bytes(int prec) { return prec == NYS_FP64 ? 8 : 4; }
 
 int32_t check_kernel(const nys_kernel &k) {

@@ -12,6 +12,7 @@ namespace nys {
 int packed_kp(int d, int prec) {
   if (prec == NYS_BF16X3) return (int)round_up(3 * d + 6, 32);
   if (prec == NYS_BF16X3_D6) return (int)round_up(6 * d + 6, 32);
+  if (prec == NYS_BF16X3_D10) return (int)round_up(10 * d + 8, 32);
   return (int)round_up(d + 2, 4);
 }
 size_t packed_elem_bytes(int prec) {
@@ -84,6 +85,31 @@ __device__ inline void split_bf16(double v, int parts, u16 *out) {
   }
 }
 
+// Split products of the low-precision distance chain.  A distance operand a is
+// split into NPART round-to-nearest bf16 parts a_0 + a_1 + ..., and the dot
+// product keeps the NT products a_p b_q of total order p + q below NPART:
+//   NT = 3  (two parts):   00, 10, 01
+//   NT = 6  (three parts): 00, 01, 10, 02, 20, 11
+//   NT = 10 (four parts):  00, 01, 10, 02, 20, 11, 03, 30, 12, 21
+// The column side stores part p of its point in segment t, the row side part q.
+template <int NT> struct SplitTerms;
+template <> struct SplitTerms<3> {
+  static constexpr int NPART = 2, NBIAS = 3;
+  static constexpr int col[3] = {0, 1, 0}, row[3] = {0, 0, 1};
+};
+template <> struct SplitTerms<6> {
+  static constexpr int NPART = 3, NBIAS = 3;
+  static constexpr int col[6] = {0, 0, 1, 0, 2, 1}, row[6] = {0, 1, 0, 2, 0, 1};
+};
+template <> struct SplitTerms<10> {
+  static constexpr int NPART = 4, NBIAS = 4;
+  static constexpr int col[10] = {0, 0, 1, 0, 2, 1, 0, 3, 1, 2}, row[10] = {0, 1, 0, 2, 0, 1, 3, 0, 2, 1};
+};
+
+// One packed point per thread.  Column side: [2 kappa x | -kappa |x|^2 | 1],
+// row side: [x | 1 | -kappa |x|^2], so that the dot product of a row point and a
+// column point is the exponent kappa (2 x.y - |x|^2 - |y|^2) of the kernel.
+// Points are centred on the column mean mu first (distances do not change).
 template <int PREC, int SIDE, int NT = 3>
 __global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu, double kappa,
                             void *out, int Kp, int64_t n_pad) {
@@ -113,48 +139,27 @@ __global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu,
       }
     }
   } else {
+    using S = SplitTerms<NT>;
     u16 *o = reinterpret_cast<u16 *>(out) + i * Kp;
     for (int k = 0; k < Kp; ++k) o[k] = 0;
     if (i < n) {
       const u16 one = bf16_bits_rne(1.0f);
+      u16 parts[S::NPART];
       for (int l = 0; l < d; ++l) {
         double v = X[i * d + l] - mu[l];
-        if constexpr (NT == 3) {
-          u16 hl[2];
-          if (SIDE == SIDE_COL) {
-            split_bf16(2.0 * kappa * v, 2, hl);   // [y_hi | y_lo | y_hi]
-            o[l] = hl[0];
-            o[d + l] = hl[1];
-            o[2 * d + l] = hl[0];
-          } else {
-            split_bf16(v, 2, hl);                 // [x_hi | x_hi | x_lo]
-            o[l] = hl[0];
-            o[d + l] = hl[0];
-            o[2 * d + l] = hl[1];
-          }
-        } else {
-          // three parts h, m, l; products hh + hm + mh + hl + lh + mm
-          u16 p3[3];
-          if (SIDE == SIDE_COL) {
-            split_bf16(2.0 * kappa * v, 3, p3);   // [h | h | m | h | l | m]
-            o[l] = p3[0]; o[d + l] = p3[0]; o[2 * d + l] = p3[1];
-            o[3 * d + l] = p3[0]; o[4 * d + l] = p3[2]; o[5 * d + l] = p3[1];
-          } else {
-            split_bf16(v, 3, p3);                 // [h | m | h | l | h | m]
-            o[l] = p3[0]; o[d + l] = p3[1]; o[2 * d + l] = p3[0];
-            o[3 * d + l] = p3[2]; o[4 * d + l] = p3[0]; o[5 * d + l] = p3[1];
-          }
-        }
+        split_bf16(SIDE == SIDE_COL ? 2.0 * kappa * v : v, S::NPART, parts);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) o[t * d + l] = parts[SIDE == SIDE_COL ? S::col[t] : S::row[t]];
       }
-      u16 b3[3];
-      split_bf16(-kappa * s, 3, b3);
+      // the squared norms enter with NBIAS parts each, against ones on the other side:
+      // column side [1 ... 1 | b_0 ... ], row side [a_0 ... | 1 ... 1]
+      u16 b[S::NBIAS];
+      split_bf16(-kappa * s, S::NBIAS, b);
       const int o0 = NT * d;
-      if (SIDE == SIDE_COL) {                   // [1 1 1 | b_hi b_mid b_lo]
-        o[o0 + 0] = one; o[o0 + 1] = one; o[o0 + 2] = one;
-        o[o0 + 3] = b3[0]; o[o0 + 4] = b3[1]; o[o0 + 5] = b3[2];
-      } else {                                  // [a_hi a_mid a_lo | 1 1 1]
-        o[o0 + 0] = b3[0]; o[o0 + 1] = b3[1]; o[o0 + 2] = b3[2];
-        o[o0 + 3] = one; o[o0 + 4] = one; o[o0 + 5] = one;
+#pragma unroll
+      for (int p = 0; p < S::NBIAS; ++p) {
+        o[o0 + p] = SIDE == SIDE_COL ? one : b[p];
+        o[o0 + S::NBIAS + p] = SIDE == SIDE_COL ? b[p] : one;
       }
     }
   }
@@ -169,11 +174,16 @@ int32_t launch_pack(const double *X, int64_t n, int d, const double *mu, const n
   if (prec == NYS_FP64) { if (side == SIDE_COL) NYS_PACK(NYS_FP64, SIDE_COL); else NYS_PACK(NYS_FP64, SIDE_ROW); }
   else if (prec == NYS_FP32) { if (side == SIDE_COL) NYS_PACK(NYS_FP32, SIDE_COL); else NYS_PACK(NYS_FP32, SIDE_ROW); }
   else if (prec == NYS_BF16X3) { if (side == SIDE_COL) NYS_PACK(NYS_BF16X3, SIDE_COL); else NYS_PACK(NYS_BF16X3, SIDE_ROW); }
-  else {
+  else if (prec == NYS_BF16X3_D6) {
     if (side == SIDE_COL)
       hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_COL, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
     else
       hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_ROW, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+  } else {
+    if (side == SIDE_COL)
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_COL, 10>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+    else
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_ROW, 10>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
   }
 #undef NYS_PACK
   NYS_LAUNCH_CHECK();
@@ -315,7 +325,7 @@ void kmv_reserve(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec, Aren
 static int ksmax_for(int prec, int Kp) {
   if (kernel_prec(prec) == NYS_BF16X3) {
     int ks = Kp / 32;
-    return ks <= 2 ? 2 : (ks <= 4 ? 4 : (ks <= 8 ? 8 : -1));
+    return ks <= 2 ? 2 : (ks <= 4 ? 4 : (ks <= 6 ? 6 : (ks <= 8 ? 8 : -1)));
   }
   int ks = Kp / 4;
   return ks <= 8 ? 8 : (ks <= 16 ? 16 : -1);

@@ -434,22 +434,26 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
   constexpr int APRE = (KSMAX * 128 + KMV2_THREADS - 1) / KMV2_THREADS;
   const int cpr = a.Kp / 8;
   const int achunks = TJ * cpr;
-  uint4 apre[APRE];
+  static_assert(APRE <= 2, "point prefetch holds at most two chunks per thread");
+  uint4 apre0 = {0, 0, 0, 0}, apre1 = {0, 0, 0, 0};   // scalars, not an array: kept in VGPRs
   auto load_points = [&](int64_t jt) {
     const uint4 *g = reinterpret_cast<const uint4 *>(Ag + jt * TJ * a.Kp);
-#pragma unroll
-    for (int k = 0; k < APRE; ++k) {
-      const int c = tid + k * KMV2_THREADS;
-      if (c < achunks) apre[k] = g[c];
+    apre0 = g[tid < achunks ? tid : achunks - 1];
+    if constexpr (APRE > 1) {
+      const int c = tid + KMV2_THREADS;
+      apre1 = g[c < achunks ? c : achunks - 1];
     }
   };
   auto store_points = [&](u16 *dst) {
-#pragma unroll
-    for (int k = 0; k < APRE; ++k) {
-      const int c = tid + k * KMV2_THREADS;
+    if (tid < achunks) {
+      const int r = tid / cpr, o = tid - r * cpr;
+      *reinterpret_cast<uint4 *>(dst + r * strideA + o * 8) = apre0;
+    }
+    if constexpr (APRE > 1) {
+      const int c = tid + KMV2_THREADS;
       if (c < achunks) {
         const int r = c / cpr, o = c - r * cpr;
-        *reinterpret_cast<uint4 *>(dst + r * strideA + o * 8) = apre[k];
+        *reinterpret_cast<uint4 *>(dst + r * strideA + o * 8) = apre1;
       }
     }
   };
@@ -490,28 +494,29 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
     const int64_t j0 = jt * TJ;
     const bool diag = a.same && (j0 < i0 + TI) && (i0 < j0 + TJ);
 
-    Op aopA[KSMAX], aopB[KSMAX];
+    // exponents of the 32 x (R*16) pair block: each column-point operand is read
+    // from LDS once and used against the R row blocks
+    f4 ta[R], tb[R];
 #pragma unroll
-    for (int s = 0; s < KSMAX; ++s) {
-      aopA[s] = (s < ks) ? load_op<NYS_BF16X3>(sAc + col16 * strideA + s * T::KSTEP + grp * T::KL)
-                         : zero_op<NYS_BF16X3>();
-      aopB[s] = (s < ks) ? load_op<NYS_BF16X3>(sAc + (16 + col16) * strideA + s * T::KSTEP + grp * T::KL)
-                         : zero_op<NYS_BF16X3>();
-    }
+    for (int r = 0; r < R; ++r) ta[r] = tb[r] = f4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+      if (s < ks) {
+        const Op a0 = load_op<NYS_BF16X3>(sAc + col16 * strideA + s * T::KSTEP + grp * T::KL);
+        const Op a1 = load_op<NYS_BF16X3>(sAc + (16 + col16) * strideA + s * T::KSTEP + grp * T::KL);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ta[r] = mfma16(a0, bop[r][s], ta[r]);
+          tb[r] = mfma16(a1, bop[r][s], tb[r]);
+        }
+      }
     bf8 phi[R], plo[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      f4 ta = {0, 0, 0, 0}, tb = {0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < KSMAX; ++s)
-        if (s < ks) {
-          ta = mfma16(aopA[s], bop[r][s], ta);
-          tb = mfma16(aopB[s], bop[r][s], tb);
-        }
       const int64_t gi = iw + r * 16 + col16;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        float t = e < 4 ? ta[e] : tb[e - 4];
+        float t = e < 4 ? ta[r][e] : tb[r][e - 4];
         const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
         if (diag && gi == gj) t = 0.0f;
         const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);

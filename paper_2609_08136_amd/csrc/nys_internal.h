@@ -84,9 +84,11 @@ struct Packed {
   int prec = 0;
 };
 
-// The tile kernels run BF16X3_D6 with the BF16X3 instantiations (only the
-// packing differs: six distance terms instead of three).
-inline int kernel_prec(int prec) { return prec == NYS_BF16X3_D6 ? NYS_BF16X3 : prec; }
+// The tile kernels run BF16X3_D6 and BF16X3_D10 with the BF16X3 instantiations
+// (only the packing differs: six or ten distance terms instead of three).
+inline int kernel_prec(int prec) {
+  return (prec == NYS_BF16X3_D6 || prec == NYS_BF16X3_D10) ? NYS_BF16X3 : prec;
+}
 
 int packed_kp(int d, int prec);
 size_t packed_elem_bytes(int prec);

@@ -218,15 +218,15 @@ def test_backward_matches_dense_gradient(nys, kind):
     assert dsig == pytest.approx(dsig_o, rel=1e-7)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_batched_lambda_grid_bf16x3_cycles_reach_true_tolerance(nys, mode):
+@pytest.mark.parametrize("prec,mode", [(3, 0), (3, 1), (4, 1)])
+def test_batched_lambda_grid_bf16x3_cycles_reach_true_tolerance(nys, prec, mode):
     """The batched workload's recipe at n = 4000 (sign labels, lambdas from 1e-7 n to
-    1e-3 n): BF16X3_D6 products, float32 CG, cycle refinement.  Every column must meet the
-    float64 true relative residual 1e-6, checked by the oracle's dense residual."""
+    1e-3 n): BF16X3_D6 / BF16X3_D10 products, float32 CG, cycle refinement.  Every column
+    must meet the float64 true relative residual 1e-6, checked by the oracle's dense residual."""
     w = ni.batched_lambda_grid(0, n=4000, nrhs=3, nlam=4, r=120)
     Om = ni.gaussian_test_matrix(w.n, w.r, 0)
-    tX, P = build(nys, w.X, Om, w.kind, w.sigma, 3)
-    X, info, rc = nys.nyspcg_solve(tX, T(w.B), w.lambdas, w.kind, w.sigma, P, tol=1e-6, prec=3,
+    tX, P = build(nys, w.X, Om, w.kind, w.sigma, prec)
+    X, info, rc = nys.nyspcg_solve(tX, T(w.B), w.lambdas, w.kind, w.sigma, P, tol=1e-6, prec=prec,
                                    refine_every=0, refine_mode=mode, refine_reduction=1e-3, max_iters=3000)
     X = X.cpu().numpy()
     K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
@@ -238,5 +238,5 @@ def test_batched_lambda_grid_bf16x3_cycles_reach_true_tolerance(nys, mode):
         assert abs(rel - info[c]["relres_true"]) <= 1e-3 * rel + 1e-12
     its = [info[l * 3]["iters"] for l in range(4)]
     refs = [info[l * 3]["refinements"] for l in range(4)]
-    print(f"mode {mode}: iters per lambda {its} refinements {refs} worst true relres {worst:.3e}")
+    print(f"prec {prec} mode {mode}: iters per lambda {its} refinements {refs} worst true relres {worst:.3e}")
     assert rc == nys.OK and worst <= 1e-6
