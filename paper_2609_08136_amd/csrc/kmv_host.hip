@@ -9,10 +9,16 @@
 namespace nys {
 
 // ------------------------------------------------------------------ packing
+// bf16 packings are padded to a whole number of 32-wide K-steps from {2, 4, 6, 8}: the
+// tiles are instantiated per step count, so the distance chain has a fixed length
+static int bf16_steps(int k) {
+  const int ks = (int)ceil_div(k, 32);
+  return ks <= 2 ? 2 : (ks <= 4 ? 4 : (ks <= 6 ? 6 : (ks <= 8 ? 8 : ks)));
+}
 int packed_kp(int d, int prec) {
-  if (prec == NYS_BF16X3) return (int)round_up(3 * d + 6, 32);
-  if (prec == NYS_BF16X3_D6) return (int)round_up(6 * d + 6, 32);
-  if (prec == NYS_BF16X3_D10) return (int)round_up(10 * d + 8, 32);
+  if (prec == NYS_BF16X3) return 32 * bf16_steps(3 * d + 6);
+  if (prec == NYS_BF16X3_D6) return 32 * bf16_steps(6 * d + 6);
+  if (prec == NYS_BF16X3_D10) return 32 * bf16_steps(10 * d + 8);
   return (int)round_up(d + 2, 4);
 }
 size_t packed_elem_bytes(int prec) {
@@ -324,8 +330,8 @@ void kmv_reserve(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec, Aren
 
 static int ksmax_for(int prec, int Kp) {
   if (kernel_prec(prec) == NYS_BF16X3) {
-    int ks = Kp / 32;
-    return ks <= 2 ? 2 : (ks <= 4 ? 4 : (ks <= 6 ? 6 : (ks <= 8 ? 8 : -1)));
+    const int ks = Kp / 32;   // packed_kp pads to one of the instantiated step counts
+    return (ks == 2 || ks == 4 || ks == 6 || ks == 8) && Kp == 32 * ks ? ks : -1;
   }
   int ks = Kp / 4;
   return ks <= 8 ? 8 : (ks <= 16 ? 16 : -1);

@@ -64,7 +64,8 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_small_kernel(KArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col16 = lane & 15, grp = lane >> 4;
-  const int ks = a.Kp / T::KSTEP;
+  // bf16 packings are padded to exactly KSMAX K-steps, so the chain length is a constant there
+  const int ks = PREC == NYS_BF16X3 ? KSMAX : a.Kp / T::KSTEP;
   const int64_t i0 = tile * TI;
   const int64_t iw = i0 + (int64_t)wave * R * 16;
   const E *Ag = reinterpret_cast<const E *>(a.Acols);
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_flash_kernel(KArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col16 = lane & 15, grp = lane >> 4;
-  const int ks = a.Kp / T::KSTEP;
+  const int ks = PREC == NYS_BF16X3 ? KSMAX : a.Kp / T::KSTEP;   // bf16 packings: exactly KSMAX steps
   const int64_t i0 = tile * TI;
   const int64_t iw = i0 + (int64_t)wave * R * 16;
   const int c0 = chunk * TM;
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col16 = lane & 15, grp = lane >> 4;
-  const int ks = a.Kp / T::KSTEP;
+  constexpr int ks = KSMAX;   // the packing pads Kp to exactly KSMAX K-steps
   const int64_t i0 = tile * TI;
   const int64_t iw = i0 + (int64_t)wave * R * 16;
   const int c0 = chunk * TM;
@@ -485,7 +486,6 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
     const int cur = (int)((jt - jt0) & 1);
     const u16 *sAc = cur ? sA1 : sA0;
     const u16 *sVh = cur ? sV1 : sV0;
-    const u16 *sVl = sVh + TM * 32;
     const bool more = jt + 1 < jt1;
     if (more) {
       stream_v(jt + 1, cur ? sV0 : sV1);
@@ -525,10 +525,17 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
         plo[r][e] = (__bf16)(kv - (float)h);
       }
     }
+    // V operands are read one column block ahead of the MFMAs that use them
+    const u16 *vrow = sVh + col16 * 32 + grp * 8;
+    bf8 vh_n = *reinterpret_cast<const bf8 *>(vrow);
+    bf8 vl_n = *reinterpret_cast<const bf8 *>(vrow + TM * 32);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      const bf8 vh = *reinterpret_cast<const bf8 *>(sVh + (cb * 16 + col16) * 32 + grp * 8);
-      const bf8 vl = *reinterpret_cast<const bf8 *>(sVl + (cb * 16 + col16) * 32 + grp * 8);
+      const bf8 vh = vh_n, vl = vl_n;
+      if (cb + 1 < NCB) {
+        vh_n = *reinterpret_cast<const bf8 *>(vrow + (cb + 1) * 16 * 32);
+        vl_n = *reinterpret_cast<const bf8 *>(vrow + TM * 32 + (cb + 1) * 16 * 32);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         acc[r][cb] = mfma16(phi[r], vh, acc[r][cb]);
