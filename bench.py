@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--refine-every", type=int, default=0)
     ap.add_argument("--refine-mode", type=int, default=1)
+    ap.add_argument("--refine-reduction", type=float, default=1e-3,
+                    help="first cycle factor of the float64 refinement cycles")
     ap.add_argument("--kmv-reps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -52,7 +54,7 @@ def parse():
                     help="with --kmv-only: first run one plain 1 GiB device copy, whose HBM counter readings "
                          "scale the kernel's (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--prec", default="bf16x3_d10", choices=["bf16x3", "bf16x3_d6", "bf16x3_d10"],
+    ap.add_argument("--prec", default="f16x3_d10", choices=["bf16x3", "bf16x3_d6", "bf16x3_d10", "f16x3_d10"],
                     help="kernel-product precision of the batched workload")
     ap.add_argument("--workload", default="batched_lambda_grid",
                     choices=["batched_lambda_grid", "plain_fp64", "matrix_free_fp32", "precision_variant",
@@ -218,6 +220,42 @@ def cpu_model() -> str:
     return platform.processor()
 
 
+# Kernel sources whose hash a committed HBM-counter summary must match to be reported.
+KERNEL_SOURCES = ["kmv_common.h", "kmv_kernels.h", "kmv_host.hip", "kmv_bf16.hip", "kmv_f16.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2609_08136_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(prec_name: str, n: int, m: int):
+    """HBM bytes per launch of the dominant kernel, from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a 1 GiB copy's reading), or None
+    when there is none for this configuration or the kernel sources changed since."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"kmv_traffic_{prec_name}_n{n}_m{m}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def time_kernel_matvec(nys, torch, X, sigma, m, prec, reps):
     """Average duration of one kernel_matvec call (HIP events on the stream it runs on)."""
     g = torch.Generator(device=X.device)
@@ -336,6 +374,7 @@ def main():
         t2 = time.perf_counter()
         Xs, info, rc = nys.nyspcg_solve(X, B, w.lambdas, w.kind, w.sigma, P, tol=w.tol, max_iters=max_iters,
                                         prec=prec, refine_every=args.refine_every, refine_mode=args.refine_mode,
+                                        refine_reduction=args.refine_reduction,
                                         workspace=ws)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
@@ -385,7 +424,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3",
+        "dtype": args.prec,
         "data": "synthetic",
         "config": {
             "workload": "batched_lambda_grid",
@@ -404,7 +443,7 @@ def main():
             "peak": round(PEAK_BF16_TFLOPS / 3.0, 1),
             "unit": "TFLOP/s",
             "frac": round(kmv_tflops / (PEAK_BF16_TFLOPS / 3.0), 4),
-            "traffic": None,
+            "traffic": counted_traffic(args.prec, n, m),
         },
         "phases_s": {"sketch": round(phases[-1][0], 3), "build": round(phases[-1][1], 3),
                      "solve": round(phases[-1][2], 3)},

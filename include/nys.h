@@ -51,6 +51,14 @@
  *                how much one float64 refinement cycle can gain when lambda is
  *                within a few decades of 1e-7 |K|; the ten-term split removes it
  *                for about 1.5x the distance work (d <= 24).
+ *    NYS_F16X3_D10  distances as NYS_BF16X3_D10; the K V product splits K and V
+ *                into fp16 parts instead (11 + 11 significand bits each, same
+ *                MFMA rate), with every column of V scaled by a power of two
+ *                so that its largest entry lies in [0.5, 1) and the scale undone
+ *                on output.  Entries far below their column's largest lose
+ *                relative (not absolute) accuracy.  About 2^-22 per product
+ *                entry against 2^-17 for the bf16 split, which is what limits
+ *                a refinement cycle once the distance error is gone (d <= 24).
  */
 #ifndef NYS_H
 #define NYS_H
@@ -74,7 +82,9 @@ extern "C" {
 #define NYS_ENOMEM        (-5) /* workspace smaller than nys_workspace_bytes() */
 
 typedef enum { NYS_RBF = 0, NYS_LAPLACIAN = 1 } nys_kind;
-typedef enum { NYS_FP64 = 0, NYS_FP32 = 1, NYS_BF16X3 = 2, NYS_BF16X3_D6 = 3, NYS_BF16X3_D10 = 4 } nys_prec;
+typedef enum {
+  NYS_FP64 = 0, NYS_FP32 = 1, NYS_BF16X3 = 2, NYS_BF16X3_D6 = 3, NYS_BF16X3_D10 = 4, NYS_F16X3_D10 = 5
+} nys_prec;
 
 /* Operations whose workspace can be queried. */
 typedef enum {
@@ -135,13 +145,21 @@ typedef struct {
  *                  join the same float64 product.
  *    refine_mode   0: after a refinement keep the search direction when the true
  *                  residual is within 0.8x..1.25x of the recursive one, else
- *                  restart the recurrence (p = z); 1: always restart
+ *                  restart the recurrence (p = z); 1: always restart;
+ *                  2: drift-controlled residual replacement (refine_every == 0):
+ *                  the refinement also measures the drift q = |r_true - r_rec| /
+ *                  |r_rec|; the search direction is kept unless q > 0.5, and the
+ *                  next cycle factor is rescaled so that the drift at its end is
+ *                  about 0.1 |r_rec| (the drift grows with the reduction a cycle
+ *                  makes, so a small replaced perturbation keeps the Krylov
+ *                  recurrence useful instead of restarting it)
  *    check_true    1: after the solve compute the float64 true relative residual
  *                  of every column into info (eq. experiment-relative-residual)
  *    max_refinements  cap on refinements per column (0: 50)
  *    refine_reduction  first cycle factor of refine_every == 0 (0: tol); later
  *                  cycles use max(refine_reduction, min(0.5, g)) with g the
- *                  true-residual reduction the previous cycle achieved
+ *                  true-residual reduction the previous cycle achieved (modes
+ *                  0, 1) or the drift rescaling above (mode 2)
  */
 typedef struct {
   double tol;

@@ -23,6 +23,7 @@ SOURCES = [
     "kmv_f64.hip",
     "kmv_f32.hip",
     "kmv_bf16.hip",
+    "kmv_f16.hip",
     "blas.hip",
     "small.hip",
     "pcg.hip",

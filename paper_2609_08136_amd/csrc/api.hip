@@ -29,12 +29,13 @@ int32_t einval(const std::string &m) {
   set_error(m);
   return NYS_EINVAL;
 }
-bool valid_prec(int p) { return p >= NYS_FP64 && p <= NYS_BF16X3_D10; }
+bool valid_prec(int p) { return p >= NYS_FP64 && p <= NYS_F16X3_D10; }
 int max_dim(int prec) {
   switch (prec) {
     case NYS_BF16X3: return 82;
     case NYS_BF16X3_D6: return 41;
-    case NYS_BF16X3_D10: return 24;
+    case NYS_BF16X3_D10:
+    case NYS_F16X3_D10: return 24;
     default: return 62;
   }
 }
@@ -283,7 +284,7 @@ int32_t check_opts(const nys_pcg_opts *o) {
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return einval("tol must be positive");
   if (o->max_iters < 0) return einval("max_iters must be >= 0");
   if (!valid_prec(o->prec)) return einval("unsupported precision");
-  if (o->refine_mode != 0 && o->refine_mode != 1) return einval("refine_mode must be 0 or 1");
+  if (o->refine_mode < 0 || o->refine_mode > 2) return einval("refine_mode must be 0, 1 or 2");
   return NYS_OK;
 }
 

@@ -21,6 +21,7 @@ namespace nys {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
 // ------------------------------------------------------------------ bf16
@@ -68,6 +69,9 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 }
 __device__ inline f4 mfma16(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(h8 a, h8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 // Row of element v (0..3) of a 16x16 MFMA result held by lane group grp = lane/16
@@ -151,6 +155,7 @@ struct KArgs {
   const void *Brows;   // packed row points (B operand rows i), [nr_pad][Kp]
   const void *V;       // small path / FP32,FP64 flash: V (nc x m, ldv); BF16 flash: V hi
   const void *V2;      // BF16 flash: V lo
+  const float *vscale; // fp16 product: per-column factor undoing the power-of-two scaling of V
   void *Out;           // nr x m (ldo) or partial [split][nr][m]
   int64_t nr, nc;
   int64_t m_pad;       // BF16 flash: width of the split V

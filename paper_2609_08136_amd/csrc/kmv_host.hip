@@ -16,6 +16,7 @@ static int bf16_steps(int k) {
   return ks <= 2 ? 2 : (ks <= 4 ? 4 : (ks <= 6 ? 6 : (ks <= 8 ? 8 : ks)));
 }
 int packed_kp(int d, int prec) {
+  prec = packing_prec(prec);
   if (prec == NYS_BF16X3) return 32 * bf16_steps(3 * d + 6);
   if (prec == NYS_BF16X3_D6) return 32 * bf16_steps(6 * d + 6);
   if (prec == NYS_BF16X3_D10) return 32 * bf16_steps(10 * d + 8);
@@ -173,6 +174,7 @@ __global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu,
 
 int32_t launch_pack(const double *X, int64_t n, int d, const double *mu, const nys_kernel &k,
                     int prec, int side, Packed *out, hipStream_t s) {
+  prec = packing_prec(prec);
   const double kappa = kernel_kappa(k, prec);
   const int64_t n_pad = out->n_pad;
   dim3 grid((unsigned)ceil_div(n_pad, 128)), block(128);
@@ -197,25 +199,74 @@ int32_t launch_pack(const double *X, int64_t n, int d, const double *mu, const n
 }
 
 // ------------------------------------------------------------------ V split
-// V (nc x m float, ldv) -> hi/lo bf16 parts in the layout [j/32][m_pad][32] with
-// the row permutation the flash tile expects: position 8 g + e of a 32-row block
-// holds row 4 g + e (e < 4) or 16 + 4 g + (e - 4) (e >= 4).
-__global__ void vsplit_kernel(const float *V, int ldv, int64_t nc, int m, int64_t m_pad,
-                              int64_t nblk, u16 *hi, u16 *lo) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over nblk*m_pad*32
-  const int64_t total = nblk * m_pad * 32;
-  if (idx >= total) return;
-  const int pos = (int)(idx & 31);
-  const int64_t rest = idx >> 5;
-  const int64_t c = rest % m_pad;
-  const int64_t jb = rest / m_pad;
-  const int g = pos >> 3, e = pos & 7;
-  const int jr = e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4);
-  const int64_t j = jb * 32 + jr;
-  float v = (j < nc && c < m) ? V[j * ldv + c] : 0.0f;
-  u16 h = bf16_bits_rne(v);
-  hi[idx] = h;
-  lo[idx] = bf16_bits_rne(v - bf16_bits_to_f(h));
+// V (nc x m float, ldv) -> hi/lo parts for the MFMA product with K.  For each block
+// of 32 rows j and 16 columns c the parts are stored as [g][c % 16][e] (g < 4,
+// e < 8: 512 elements): lane group g of the tile reads the eight rows that the
+// exponent MFMA left in its registers, rows 4 g + e (e < 4) and 16 + 4 g + e - 4
+// (e >= 4), and the 16 lanes of a group read 256 contiguous bytes.  One thread
+// writes one 8-element run (16 bytes per part).
+__device__ inline int vsplit_row(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4); }
+
+template <bool F16>
+__global__ void vsplit_kernel(const float *V, int ldv, int64_t nc, int m, int64_t m_pad, int64_t nblk,
+                              const float *scale, u16 *hi, u16 *lo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // over nblk * m_pad * 4 runs
+  if (t >= nblk * m_pad * 4) return;
+  const int c16 = (int)(t & 15);
+  const int g = (int)((t >> 4) & 3);
+  const int64_t rest = t >> 6;
+  const int64_t cg = rest % (m_pad / 16);
+  const int64_t jb = rest / (m_pad / 16);
+  const int64_t c = cg * 16 + c16;
+  const float sc = (F16 && c < m) ? scale[c] : 1.0f;
+  u16 h[8], l[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t j = jb * 32 + vsplit_row(g, e);
+    const float v = (j < nc && c < m) ? V[j * ldv + c] * sc : 0.0f;
+    if constexpr (F16) {
+      const _Float16 hv = (_Float16)v;
+      h[e] = __builtin_bit_cast(u16, hv);
+      l[e] = __builtin_bit_cast(u16, (_Float16)(v - (float)hv));
+    } else {
+      h[e] = bf16_bits_rne(v);
+      l[e] = bf16_bits_rne(v - bf16_bits_to_f(h[e]));
+    }
+  }
+  const int64_t o = jb * m_pad * 32 + cg * 512 + g * 128 + c16 * 8;
+  uint4 hv, lv;
+  hv.x = h[0] | ((uint32_t)h[1] << 16); hv.y = h[2] | ((uint32_t)h[3] << 16);
+  hv.z = h[4] | ((uint32_t)h[5] << 16); hv.w = h[6] | ((uint32_t)h[7] << 16);
+  lv.x = l[0] | ((uint32_t)l[1] << 16); lv.y = l[2] | ((uint32_t)l[3] << 16);
+  lv.z = l[4] | ((uint32_t)l[5] << 16); lv.w = l[6] | ((uint32_t)l[7] << 16);
+  *reinterpret_cast<uint4 *>(hi + o) = hv;
+  *reinterpret_cast<uint4 *>(lo + o) = lv;
+}
+
+// fp16 product: per-column power-of-two scales.  Pass 1: max |V| of each column over
+// a range of rows (threads run along the columns, so reads are coalesced).
+constexpr int VMAX_BLOCKS = 128;
+__global__ void col_absmax_partial_kernel(const float *V, int ldv, int64_t nc, int m, int64_t rows_per,
+                                          float *partial) {
+  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = r0 + rows_per < nc ? r0 + rows_per : nc;
+  float mx = 0.0f;
+  for (int64_t j = r0; j < r1; ++j) mx = fmaxf(mx, fabsf(V[j * ldv + c]));
+  partial[(int64_t)blockIdx.x * m + c] = mx;
+}
+// Pass 2: scale[c] = 2^-e with max |V[:, c]| = f 2^e, f in [0.5, 1) (1 for a zero
+// column), and its inverse for the output.
+__global__ void col_scale_kernel(const float *partial, int nb, int m, float *scale, float *iscale) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  float mx = 0.0f;
+  for (int b = 0; b < nb; ++b) mx = fmaxf(mx, partial[(int64_t)b * m + c]);
+  int e = 0;
+  if (mx > 0.0f && mx <= 3.0e38f) (void)frexpf(mx, &e);
+  scale[c] = ldexpf(1.0f, -e);
+  iscale[c] = ldexpf(1.0f, e);
 }
 
 // ------------------------------------------------------------------ split reduce
@@ -257,6 +308,7 @@ static int small_r_for(int prec, int mm) {
 
 KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   (void)Kp;
+  const bool f16v = f16_product(prec);
   prec = kernel_prec(prec);
   KmvPlan p;
   const int mm_cap = prec == NYS_FP64 ? 8 : 16;
@@ -286,8 +338,14 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       if (ov.tm) p.tm = ov.tm;
       if (ov.r) p.r = ov.r;
     }
-    // BF16X3 chunks of >= 64 columns run on the pipelined eight-wave tile
+    // BF16X3 chunks of >= 64 columns run on the pipelined eight-wave tile; the fp16
+    // product exists only there (every chunk width)
     if (prec == NYS_BF16X3 && p.tm >= 64 && p.r == 2) p.waves = 8;
+    if (f16v) {
+      p.r = 2;
+      p.waves = 8;
+      p.f16v = 1;
+    }
   }
   if (p.path == 0 || p.waves != 8) {
     p.waves = 4;
@@ -313,6 +371,8 @@ void kmv_scratch_sizes(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec
   const size_t fb = prec == NYS_FP64 ? 8 : 4;
   *partial_bytes = p.splits > 1 ? (size_t)p.splits * nr * m * fb : 0;
   *vsplit_elems = (p.path == 1 && prec == NYS_BF16X3) ? (size_t)ceil_div(nc, 32) * p.m_pad * 32 : 0;
+  // fp16 product: column maxima and scales (floats) follow the split V in each part
+  if (p.path == 1 && p.f16v) *vsplit_elems += 2 * (size_t)(VMAX_BLOCKS + 2) * m;
 }
 
 void kmv_reserve(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec, Arena &ws,
@@ -384,11 +444,32 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, c
   if (plan.path == 1) {
     chunks = (int)ceil_div(m, plan.tm);
     a.chunks = chunks;
-    if (prec == NYS_BF16X3) {
+    if (prec == NYS_BF16X3 && plan.f16v) {
       const int64_t nblk = ceil_div(cols.n, 32);
       const int64_t total = nblk * plan.m_pad * 32;
-      hipLaunchKernelGGL(vsplit_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s,
-                         reinterpret_cast<const float *>(V), ldv, cols.n, m, plan.m_pad, nblk,
+      float *fs = reinterpret_cast<float *>(reinterpret_cast<u16 *>(vlo) + total);
+      float *vpart = fs, *scale = fs + (size_t)VMAX_BLOCKS * m, *iscale = scale + m;
+      const int nbm = (int)std::max<int64_t>(1, std::min<int64_t>(VMAX_BLOCKS, ceil_div(cols.n, 4096)));
+      const int64_t rows_per = ceil_div(cols.n, nbm);
+      hipLaunchKernelGGL(col_absmax_partial_kernel, dim3((unsigned)nbm, (unsigned)ceil_div(m, 256)), dim3(256), 0,
+                         s, reinterpret_cast<const float *>(V), ldv, cols.n, m, rows_per, vpart);
+      NYS_LAUNCH_CHECK();
+      hipLaunchKernelGGL(col_scale_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, vpart, nbm, m,
+                         scale, iscale);
+      NYS_LAUNCH_CHECK();
+      hipLaunchKernelGGL(vsplit_kernel<true>, dim3((unsigned)ceil_div(total / 8, 256)), dim3(256), 0, s,
+                         reinterpret_cast<const float *>(V), ldv, cols.n, m, plan.m_pad, nblk, scale,
+                         reinterpret_cast<u16 *>(vhi), reinterpret_cast<u16 *>(vlo));
+      NYS_LAUNCH_CHECK();
+      a.V = vhi;
+      a.V2 = vlo;
+      a.vscale = iscale;
+      a.m_pad = plan.m_pad;
+    } else if (prec == NYS_BF16X3) {
+      const int64_t nblk = ceil_div(cols.n, 32);
+      const int64_t total = nblk * plan.m_pad * 32;
+      hipLaunchKernelGGL(vsplit_kernel<false>, dim3((unsigned)ceil_div(total / 8, 256)), dim3(256), 0, s,
+                         reinterpret_cast<const float *>(V), ldv, cols.n, m, plan.m_pad, nblk, nullptr,
                          reinterpret_cast<u16 *>(vhi), reinterpret_cast<u16 *>(vlo));
       NYS_LAUNCH_CHECK();
       a.V = vhi;
@@ -408,6 +489,7 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, c
   int32_t rc;
   if (prec == NYS_FP64) rc = kmv_dispatch_f64(plan, k.kind, deriv, ksmax, a, grid, s);
   else if (prec == NYS_FP32) rc = kmv_dispatch_f32(plan, k.kind, deriv, ksmax, a, grid, s);
+  else if (plan.path == 1 && plan.f16v) rc = kmv_dispatch_f16(plan, k.kind, deriv, ksmax, a, grid, s);
   else rc = kmv_dispatch_bf16(plan, k.kind, deriv, ksmax, a, grid, s);
   NYS_RETURN_IF(rc);
   NYS_LAUNCH_CHECK();

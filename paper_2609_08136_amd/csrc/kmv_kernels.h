@@ -295,8 +295,8 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_flash_kernel(KArgs a) {
       const u16 *sl = sh + TM * 32;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
-        bf8 vh = *reinterpret_cast<const bf8 *>(sh + (cb * 16 + col16) * 32 + grp * 8);
-        bf8 vl = *reinterpret_cast<const bf8 *>(sl + (cb * 16 + col16) * 32 + grp * 8);
+        bf8 vh = *reinterpret_cast<const bf8 *>(sh + cb * 512 + grp * 128 + col16 * 8);
+        bf8 vl = *reinterpret_cast<const bf8 *>(sl + cb * 512 + grp * 128 + col16 * 8);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           acc[r][cb] = mfma16(phi[r], vh, acc[r][cb]);
@@ -372,12 +372,20 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_flash_kernel(KArgs a) {
 // global-to-LDS loads (no registers) and the packed points of tile t+1 wait in
 // registers; one barrier per tile.  Per tile and wave: 2 R KS MFMAs for the
 // exponents, 3 R TM/16 for K V.
+// F16V: the K V product splits K and V into fp16 parts instead of bf16 (V arrives
+// scaled per column by a power of two, undone on output): 11 + 11 significand bits
+// per operand instead of 8 + 8 at the same MFMA rate.
 constexpr int KMV2_THREADS = 512;
 
-template <int KIND, int KSMAX, int TM>
+template <bool F16V> struct ProdType { using V = bf8; using S = __bf16; };
+template <> struct ProdType<true> { using V = h8; using S = _Float16; };
+
+template <int KIND, int KSMAX, int TM, bool F16V = false>
 __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
   using T = Tr<NYS_BF16X3>;
   using Op = typename T::Op;
+  using PV = typename ProdType<F16V>::V;   // operand vector of the K V product
+  using PS = typename ProdType<F16V>::S;
   constexpr int R = 2, WAVES = KMV2_THREADS / 64;
   constexpr int TJ = 32, TI = WAVES * R * 16, NCB = TM / 16;
   constexpr int VCH = TM * 4;                      // 16-byte chunks per V part per tile
@@ -510,7 +518,7 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
           tb[r] = mfma16(a1, bop[r][s], tb[r]);
         }
       }
-    bf8 phi[R], plo[R];
+    PV phi[R], plo[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t gi = iw + r * 16 + col16;
@@ -520,21 +528,22 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
         const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
         if (diag && gi == gj) t = 0.0f;
         const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);
-        const __bf16 h = (__bf16)kv;
+        const PS h = (PS)kv;
         phi[r][e] = h;
-        plo[r][e] = (__bf16)(kv - (float)h);
+        plo[r][e] = (PS)(kv - (float)h);
       }
     }
     // V operands are read one column block ahead of the MFMAs that use them
-    const u16 *vrow = sVh + col16 * 32 + grp * 8;
-    bf8 vh_n = *reinterpret_cast<const bf8 *>(vrow);
-    bf8 vl_n = *reinterpret_cast<const bf8 *>(vrow + TM * 32);
+    // 16 lanes of a lane group read 256 contiguous bytes (no LDS bank conflicts)
+    const u16 *vrow = sVh + grp * 128 + col16 * 8;
+    PV vh_n = *reinterpret_cast<const PV *>(vrow);
+    PV vl_n = *reinterpret_cast<const PV *>(vrow + TM * 32);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      const bf8 vh = vh_n, vl = vl_n;
+      const PV vh = vh_n, vl = vl_n;
       if (cb + 1 < NCB) {
-        vh_n = *reinterpret_cast<const bf8 *>(vrow + (cb + 1) * 16 * 32);
-        vl_n = *reinterpret_cast<const bf8 *>(vrow + TM * 32 + (cb + 1) * 16 * 32);
+        vh_n = *reinterpret_cast<const PV *>(vrow + (cb + 1) * 16 * 32);
+        vl_n = *reinterpret_cast<const PV *>(vrow + TM * 32 + (cb + 1) * 16 * 32);
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -558,7 +567,8 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
         const int64_t i = iw + r * 16 + out_row<NYS_BF16X3>(grp, v);
         const int c = c0 + cb * 16 + col16;
         if (i < a.nr && c < a.m) {
-          const float sum = acc[r][cb][v];
+          float sum = acc[r][cb][v];
+          if constexpr (F16V) sum *= a.vscale[c];
           if (a.partial) {
             O[((int64_t)split * a.nr + i) * a.m + c] = sum;
           } else {
@@ -598,6 +608,8 @@ int32_t kmv_dispatch_f64(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs
 int32_t kmv_dispatch_f32(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
                          hipStream_t s);
 int32_t kmv_dispatch_bf16(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
+                          hipStream_t s);
+int32_t kmv_dispatch_f16(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
                           hipStream_t s);
 
 }  // namespace nys

@@ -84,11 +84,15 @@ struct Packed {
   int prec = 0;
 };
 
-// The tile kernels run BF16X3_D6 and BF16X3_D10 with the BF16X3 instantiations
-// (only the packing differs: six or ten distance terms instead of three).
+// The tile kernels run BF16X3_D6, BF16X3_D10 and F16X3_D10 with the BF16X3
+// instantiations (the packing differs: six or ten distance terms instead of
+// three; F16X3_D10 also switches the K V product to fp16 parts).
 inline int kernel_prec(int prec) {
-  return (prec == NYS_BF16X3_D6 || prec == NYS_BF16X3_D10) ? NYS_BF16X3 : prec;
+  return (prec == NYS_BF16X3_D6 || prec == NYS_BF16X3_D10 || prec == NYS_F16X3_D10) ? NYS_BF16X3 : prec;
 }
+inline bool f16_product(int prec) { return prec == NYS_F16X3_D10; }
+// the distance packing of a precision (F16X3_D10 packs as BF16X3_D10)
+inline int packing_prec(int prec) { return prec == NYS_F16X3_D10 ? NYS_BF16X3_D10 : prec; }
 
 int packed_kp(int d, int prec);
 size_t packed_elem_bytes(int prec);
@@ -112,6 +116,7 @@ struct KmvPlan {
   int splits = 1;        // split of the column (j) range
   int jsteps = 0;        // j tiles per split
   int64_t m_pad = 0;     // flash BF16: padded width of the split V
+  int f16v = 0;          // flash: fp16 K V product with column-scaled V
 };
 
 // Decide the launch shape for an (nr, nc, m, prec) product.

@@ -26,6 +26,10 @@ int32_t p_update(T *P, const T *Z, const double *beta, int64_t n, int m, hipStre
 template <class T>
 int32_t init_rhs(const double *B, int nrhs, const int *bcol, T *R, T *X, int64_t n, int m, hipStream_t s);
 int32_t flush_x(float *X, double *X64, int64_t count, hipStream_t s);
+// squared 2-norm of R64[:, t] - R[:, idx[t]] for t < ns into partials (colfinal(n, ns) sums them)
+template <class T>
+int32_t gapnorm(const double *R64, int ns, const T *R, int ma, const int *idx, int64_t n, double *partial,
+                hipStream_t s);
 int32_t residual64(const double *B, int nrhs, const int *bcol, const double *lam, const double *X64,
                    double *KX, float *R32, int64_t n, int m, hipStream_t s);
 template <class T>

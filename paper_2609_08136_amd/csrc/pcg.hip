@@ -125,6 +125,51 @@ int32_t colfinal(const double *partial, int64_t n, int m, int mode, double *out,
   return NYS_OK;
 }
 
+// partial = sum (R64[:, t] - R[:, idx[t]])^2 over the ns refined columns: how far the
+// recursive residual R (ma columns) had drifted from the float64 one (idx null: t)
+template <class T>
+__global__ __launch_bounds__(256) void gap_kernel(const double *R64, int ns, const T *R, int ma, const int *idx,
+                                                  int64_t n, int64_t rows_per, double *partial) {
+  __shared__ double red[256];
+  const int cw = blockDim.x, ry = blockDim.y;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = std::min<int64_t>(n, r0 + rows_per);
+  for (int c0 = 0; c0 < ns; c0 += cw) {
+    const int c = c0 + tx;
+    double s = 0.0;
+    if (c < ns) {
+      const int cr = idx ? idx[c] : c;
+      for (int64_t i = r0 + ty; i < r1; i += ry) {
+        const double d = R64[i * ns + c] - (double)R[i * ma + cr];
+        s += d * d;
+      }
+    }
+    red[ty * cw + tx] = s;
+    __syncthreads();
+    for (int w = ry / 2; w > 0; w >>= 1) {
+      if (ty < w) red[ty * cw + tx] += red[(ty + w) * cw + tx];
+      __syncthreads();
+    }
+    if (ty == 0 && c < ns) partial[(int64_t)blockIdx.x * ns + c] = red[tx];
+    __syncthreads();
+  }
+}
+
+template <class T>
+int32_t gapnorm(const double *R64, int ns, const T *R, int ma, const int *idx, int64_t n, double *partial,
+                hipStream_t s) {
+  const ColRedShape sh = colred_shape(n, ns);
+  hipLaunchKernelGGL((gap_kernel<T>), dim3(sh.nb), dim3(sh.cw, sh.ry), 0, s, R64, ns, R, ma, idx, n, sh.rows_per,
+                     partial);
+  NYS_LAUNCH_CHECK();
+  return NYS_OK;
+}
+template int32_t gapnorm<float>(const double *, int, const float *, int, const int *, int64_t, double *,
+                                hipStream_t);
+template int32_t gapnorm<double>(const double *, int, const double *, int, const int *, int64_t, double *,
+                                 hipStream_t);
+
 template int32_t colred<float>(int, const float *, float *, float *, float *, int64_t, int, const double *,
                                double *, hipStream_t, double *);
 template int32_t colred<double>(int, const double *, double *, double *, double *, int64_t, int,

@@ -14,9 +14,13 @@
 // r = b - (K + lambda I) x64 in float64, replacing the recursive residual) once
 // its recursive residual has fallen by its cycle factor delta since the last
 // refinement; delta follows the reduction the previous cycle actually achieved,
-// so iterations are not spent below the precision floor.  When the true
-// residual exceeds the recursive one by more than 4x the recurrence restarts
-// (p = z), otherwise the search direction is kept.
+// so iterations are not spent below the precision floor.  Mode 1 restarts the
+// recurrence (p = z) after every refinement; mode 0 keeps the search direction
+// when the replaced residual is within 25% of the recursive one.  Mode 2 measures
+// the drift q = |r_true - r_rec| / |r_rec| at each refinement, keeps p unless
+// q > 0.5, and rescales the next cycle factor by q / 0.1: the drift accumulated
+// over a cycle grows with the reduction the cycle makes, so cycles are sized to
+// end with about a 10% replacement, which the recurrence absorbs without a restart.
 #pragma once
 
 struct Slot {
@@ -89,7 +93,8 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
     sl[c].bb = bb[c];
   }
 
-  std::vector<double> rr_h(mtot), rt_h(mtot);
+  std::vector<double> rr_h(mtot), rt_h(mtot), gap_h(mtot);
+  const bool drift = o.refine_mode == 2;
   std::vector<int> flag_h(mtot);
   bool breakdown = false;
 
@@ -146,16 +151,29 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
       NYS_RETURN_IF(gather_cols<double>(X64, ma, sp.idx, ns, Sp64, n, s));
       NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, Sp64, ns, ns, R64, ns, 1.0, 0.0, s));
       NYS_RETURN_IF(residual64(B, nrhs, sp.bcol2, sp.lam2, Sp64, R64, nullptr, n, ns, s));
+      if (drift) NYS_RETURN_IF(gapnorm<T>(R64, ns, R, ma, sp.idx, n, sp.red, s));
+      if (drift) NYS_RETURN_IF(colfinal(sp.red, n, ns, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
+      if (drift) NYS_CHECK_HIP(hipMemcpyAsync(gap_h.data(), sp.tmpc, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
       NYS_RETURN_IF(scatter_cols_d2f(R64, ns, sp.idx, reinterpret_cast<float *>(R), ma, n, s));
     } else {
       NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, X64, ma, ma, R64, ma, 1.0, 0.0, s));
-      NYS_RETURN_IF(residual64(B, nrhs, sp.bcol, sp.lam, X64, R64, reinterpret_cast<float *>(R), n, ma, s));
+      NYS_RETURN_IF(residual64(B, nrhs, sp.bcol, sp.lam, X64, R64, drift ? nullptr : reinterpret_cast<float *>(R),
+                               n, ma, s));
+      if (drift) {
+        NYS_RETURN_IF(gapnorm<T>(R64, ma, R, ma, nullptr, n, sp.red, s));
+        NYS_RETURN_IF(colfinal(sp.red, n, ma, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
+        NYS_CHECK_HIP(hipMemcpyAsync(gap_h.data(), sp.tmpc, sizeof(double) * ma, hipMemcpyDeviceToHost, s));
+        NYS_RETURN_IF(launch_copy_d2f(R64, reinterpret_cast<float *>(R), n * (int64_t)ma, s));
+      }
     }
     NYS_RETURN_IF(colred<double>(0, R64, R64, nullptr, nullptr, n, ns, nullptr, sp.red, s));
     NYS_RETURN_IF(colfinal(sp.red, n, ns, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
     NYS_CHECK_HIP(hipMemcpyAsync(rt_h.data(), sp.tmpc, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
     NYS_CHECK_HIP(hipStreamSynchronize(s));
-    for (int t = 0; t < ns; ++t) rt_h[t] = std::sqrt(std::max(rt_h[t], 0.0) / sl[sel[t]].bb);
+    for (int t = 0; t < ns; ++t) {
+      rt_h[t] = std::sqrt(std::max(rt_h[t], 0.0) / sl[sel[t]].bb);
+      if (drift) gap_h[t] = std::sqrt(std::max(gap_h[t], 0.0) / sl[sel[t]].bb);   // relative to |b|
+    }
     return NYS_OK;
   };
 
@@ -264,9 +282,16 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
           const double g = rt / c.rstart;
           c.rstart = rt;
           c.rmin = rt;
-          if (delta0 > 0.0) c.delta = std::max(delta0, std::min(0.5, g));
-          // keeping p is only sound when the replacement barely moved the residual
-          c.restart = (o.refine_mode == 1 || rt > 1.25 * rel[q] || rt < 0.8 * rel[q]) ? 1 : 0;
+          if (drift) {
+            // drift relative to the recursive residual it replaced
+            const double qd = gap_h[t] / std::max(rel[q], 1e-300);
+            if (delta0 > 0.0) c.delta = std::min(0.5, std::max(1e-4, c.delta * std::max(qd, 1e-3) / 0.1));
+            c.restart = qd > 0.5 ? 1 : 0;
+          } else {
+            if (delta0 > 0.0) c.delta = std::max(delta0, std::min(0.5, g));
+            // keeping p is only sound when the replacement barely moved the residual
+            c.restart = (o.refine_mode == 1 || rt > 1.25 * rel[q] || rt < 0.8 * rel[q]) ? 1 : 0;
+          }
           if (c.refs >= max_refs) stop[q] = 1;
         }
         if (verbose) {

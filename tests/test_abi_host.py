@@ -73,6 +73,7 @@ def test_kernel_matvec_argument_errors(lib):
     assert args(k, d=63, prec=nys.FP32) == nys.EINVAL
     assert args(k, d=42, prec=nys.BF16X3_D6) == nys.EINVAL
     assert args(k, d=25, prec=nys.BF16X3_D10) == nys.EINVAL
+    assert args(k, d=25, prec=nys.F16X3_D10) == nys.EINVAL
     assert args(k, deriv=2) == nys.EINVAL
     assert b"sigma" in lib.nys_last_error() or True
     # null workspace
@@ -91,8 +92,8 @@ def test_solve_argument_errors(lib):
     assert solve([-1.0]) == nys.EINVAL
     assert solve([float("nan")]) == nys.EINVAL
     assert solve([1.0], tol=0.0) == nys.EINVAL
-    assert solve([1.0], prec=5) == nys.EINVAL
-    assert solve([1.0], mode=2) == nys.EINVAL
+    assert solve([1.0], prec=6) == nys.EINVAL
+    assert solve([1.0], mode=3) == nys.EINVAL
     assert solve([1.0], max_iters=-1) == nys.EINVAL
     assert solve([1.0], nrhs=0) == nys.EINVAL
     assert b"lambda" in lib.nys_last_error() or b"nrhs" in lib.nys_last_error()

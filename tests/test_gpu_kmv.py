@@ -21,7 +21,7 @@ import oracle as o
 
 pytestmark = pytest.mark.gpu
 
-U = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -16, 3: 2.0 ** -16, 4: 2.0 ** -16}
+U = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -16, 3: 2.0 ** -16, 4: 2.0 ** -16, 5: 2.0 ** -16}
 
 
 def bound(Xr, Xc, V, kind, sigma, prec, deriv=0):
@@ -56,7 +56,7 @@ def run(nys, Xr, Xc, V, kind, sigma, prec, deriv=0, alpha=1.0, beta=0.0, out=Non
 
 
 def check(nys, n_r, n_c, d, m, kind, prec, seed=0, same=True, deriv=0, heavy=False):
-    if prec == 4 and d > 24:
+    if prec in (4, 5) and d > 24:
         # ten-term split: the packed K extent 10 d + 8 must fit the 256-wide tile
         with pytest.raises(nys.NysError, match="d out of range"):
             run(nys, np.zeros((2, d)), np.zeros((2, d)), np.zeros((2, m)), kind, 1.0, prec, deriv)
@@ -80,7 +80,7 @@ def check(nys, n_r, n_c, d, m, kind, prec, seed=0, same=True, deriv=0, heavy=Fal
     return got, ref
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("n,d,m", [(1, 3, 1), (31, 10, 1), (257, 16, 3), (2000, 10, 1), (700, 20, 8),
                                    (513, 33, 16), (300, 1, 5)])
@@ -88,7 +88,7 @@ def test_matvec_small_m(nys, prec, kind, n, d, m):
     check(nys, n, n, d, m, kind, prec, seed=n + d + m)
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("n,d,m", [(100, 10, 17), (1000, 16, 64), (777, 20, 50), (1500, 32, 200),
                                    (2000, 10, 300)])
@@ -161,7 +161,7 @@ def test_matvec_large_sampled_rows(nys):
     tX = torch.from_numpy(X).to(dev)
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(X.shape[0], 24, replace=False))
-    for m, prec in ((1, 2), (512, 2), (512, 3), (512, 4), (64, 4)):
+    for m, prec in ((1, 2), (512, 2), (512, 3), (512, 4), (64, 4), (512, 5), (40, 5)):
         V = rng.standard_normal((X.shape[0], m)).astype(np.float32)
         tV = torch.from_numpy(V).to(dev)
         print(f"case n=1e6 d=16 m={m} prec={prec}", flush=True)
@@ -194,3 +194,21 @@ def test_six_term_distance_is_more_accurate(nys):
     print(f"max relative entry error: 3-term {e3:.3e}, 6-term {e6:.3e}")
     assert e3 < 2.0 ** -11
     assert e6 < e3 / 16 and e6 < 2.0 ** -18
+
+
+def test_fp16_product_is_more_accurate(nys):
+    """F16X3_D10 splits K and the column-scaled V into fp16 parts for the second MFMA
+    (11 + 11 significand bits) where BF16X3_D10 uses bf16 parts (8 + 8).  With unit
+    vectors as columns (17 of them: the MFMA product path) every output is a single
+    kernel entry, so the entry error of the two products is compared directly."""
+    rng = np.random.default_rng(22)
+    X = rng.standard_normal((3000, 16))
+    J = rng.choice(3000, 17, replace=False)
+    V = np.zeros((3000, 17))
+    V[J, np.arange(17)] = 1.0
+    ref = o.kernel_matrix(X, X, o.RBF, 4.0)[:, J]
+    e_bf = np.max(np.abs(run(nys, X, X, V, o.RBF, 4.0, 4) - ref) / ref)
+    e_h = np.max(np.abs(run(nys, X, X, V, o.RBF, 4.0, 5) - ref) / ref)
+    print(f"max relative entry error: bf16 product {e_bf:.3e}, fp16 product {e_h:.3e}")
+    assert e_bf < 2.0 ** -15
+    assert e_h < e_bf / 8 and e_h < 2.0 ** -19

@@ -218,10 +218,10 @@ def test_backward_matches_dense_gradient(nys, kind):
     assert dsig == pytest.approx(dsig_o, rel=1e-7)
 
 
-@pytest.mark.parametrize("prec,mode", [(3, 0), (3, 1), (4, 1)])
+@pytest.mark.parametrize("prec,mode", [(3, 0), (3, 1), (4, 1), (5, 1)])
 def test_batched_lambda_grid_bf16x3_cycles_reach_true_tolerance(nys, prec, mode):
     """The batched workload's recipe at n = 4000 (sign labels, lambdas from 1e-7 n to
-    1e-3 n): BF16X3_D6 / BF16X3_D10 products, float32 CG, cycle refinement.  Every column
+    1e-3 n): BF16X3_D6 / BF16X3_D10 / F16X3_D10 products, float32 CG, cycle refinement.  Every column
     must meet the float64 true relative residual 1e-6, checked by the oracle's dense residual."""
     w = ni.batched_lambda_grid(0, n=4000, nrhs=3, nlam=4, r=120)
     Om = ni.gaussian_test_matrix(w.n, w.r, 0)
