@@ -24,6 +24,7 @@ SOURCES = [
     "kmv_f32.hip",
     "kmv_bf16.hip",
     "kmv_f16.hip",
+    "kmv_f64p.hip",
     "blas.hip",
     "small.hip",
     "pcg.hip",

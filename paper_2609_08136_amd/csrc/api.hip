@@ -77,20 +77,21 @@ void plan_kmv(KmvBufs &b, int64_t nr, int64_t nc, int d, int m_lo, int m_max, in
   b.mpart = ws.take<double>(col_mean_partial_elems(nc, d));
   plan_points(b.rows, nr, d, prec, ws);
   plan_points(b.cols, nc, d, prec, ws);
-  size_t pb = 0, ve = 0, a = 0, e = 0;
+  size_t pb = 0, ve = 0, vl = 0, a = 0, e = 0, l = 0;
   for (int m = std::max(1, m_lo); m <= m_max; ++m) {
     KmvPlan p = kmv_plan(nr, nc, m, prec, b.rows.Kp);
-    kmv_scratch_sizes(p, nr, nc, m, prec, &a, &e);
+    kmv_scratch_sizes(p, nr, nc, m, prec, &a, &e, &l);
     pb = std::max(pb, a);
     ve = std::max(ve, e);
+    vl = std::max(vl, l);
   }
   // the derivative product runs in chunks of <= 4 columns with the 4-column plan
   const KmvPlan p4 = kmv_plan(nr, nc, 4, prec, b.rows.Kp);
-  kmv_scratch_sizes(p4, nr, nc, std::min(4, std::max(1, m_max)), prec, &a, &e);
+  kmv_scratch_sizes(p4, nr, nc, std::min(4, std::max(1, m_max)), prec, &a, &e, &l);
   pb = std::max(pb, a);
   b.partial = pb ? ws.take<char>(pb) : nullptr;
   b.vhi = ve ? ws.take<bf16bits>(ve) : nullptr;
-  b.vlo = ve ? ws.take<bf16bits>(ve) : nullptr;
+  b.vlo = vl ? ws.take<bf16bits>(vl) : nullptr;
 }
 
 int32_t prep_points(KmvBufs &b, const nys_kernel &k, int prec, const double *Xr, const double *Xc,

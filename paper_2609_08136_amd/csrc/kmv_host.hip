@@ -243,6 +243,28 @@ __global__ void vsplit_kernel(const float *V, int ldv, int64_t nc, int m, int64_
   *reinterpret_cast<uint4 *>(lo + o) = lv;
 }
 
+// V (nc x m double, ldv) -> the float64 tile's layout: per 32-row tile jt and column
+// chunk of tm, [h][v][cb][g][c % 16] holds V[32 jt + 16 h + 4 v + g][chunk tm + 16 cb + c % 16]
+// (zero outside V).  Threads run in output order; 16 consecutive threads read 16
+// consecutive columns.
+__global__ void vperm64_kernel(const double *V, int ldv, int64_t nc, int m, int tm, int chunks, int64_t total,
+                               double *Vp) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int c16 = (int)(idx & 15), g = (int)((idx >> 4) & 3);
+  int64_t rest = idx >> 6;
+  const int ncb = tm / 16;
+  const int cb = (int)(rest % ncb);
+  rest /= ncb;
+  const int v = (int)(rest & 3), h = (int)((rest >> 2) & 1);
+  rest >>= 3;
+  const int chunk = (int)(rest % chunks);
+  const int64_t jt = rest / chunks;
+  const int64_t j = jt * 32 + 16 * h + 4 * v + g;
+  const int64_t c = (int64_t)chunk * tm + cb * 16 + c16;
+  Vp[idx] = (j < nc && c < m) ? V[j * ldv + c] : 0.0;
+}
+
 // fp16 product: per-column power-of-two scales.  Pass 1: max |V| of each column over
 // a range of rows (threads run along the columns, so reads are coalesced).
 constexpr int VMAX_BLOCKS = 128;
@@ -311,7 +333,8 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   const bool f16v = f16_product(prec);
   prec = kernel_prec(prec);
   KmvPlan p;
-  const int mm_cap = prec == NYS_FP64 ? 8 : 16;
+  // float64: the pipelined tile beats the row-sum tile from 5 columns on (16-column chunks)
+  const int mm_cap = prec == NYS_FP64 ? 4 : 16;
   Override ov;
   {
     std::lock_guard<std::mutex> lk(g_ovr_mu);
@@ -328,10 +351,10 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : (m <= 128 ? 128 : 256));
       p.r = 2;
     } else if (prec == NYS_FP32) {
-      p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : 128);
+      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : 64);   // 128 would exceed the float64 tile's registers
       p.r = 2;
     } else {
-      p.tm = m <= 32 ? 32 : 64;
+      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : 64);   // 128 would exceed the float64 tile's registers
       p.r = 2;
     }
     if (ov.set && ov.path == 1) {
@@ -346,6 +369,8 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.waves = 8;
       p.f16v = 1;
     }
+    // float64 chunks run on the pipelined eight-wave float64 tile
+    if (prec == NYS_FP64 && p.r == 2) p.waves = 8;
   }
   if (p.path == 0 || p.waves != 8) {
     p.waves = 4;
@@ -366,26 +391,29 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
 }
 
 void kmv_scratch_sizes(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec,
-                       size_t *partial_bytes, size_t *vsplit_elems) {
+                       size_t *partial_bytes, size_t *vsplit_elems, size_t *vlo_elems) {
   prec = kernel_prec(prec);
   const size_t fb = prec == NYS_FP64 ? 8 : 4;
   *partial_bytes = p.splits > 1 ? (size_t)p.splits * nr * m * fb : 0;
-  *vsplit_elems = (p.path == 1 && prec == NYS_BF16X3) ? (size_t)ceil_div(nc, 32) * p.m_pad * 32 : 0;
-  // fp16 product: column maxima and scales (floats) follow the split V in each part
-  if (p.path == 1 && p.f16v) *vsplit_elems += 2 * (size_t)(VMAX_BLOCKS + 2) * m;
+  *vsplit_elems = *vlo_elems = 0;
+  if (p.path == 1 && prec == NYS_BF16X3) {
+    *vsplit_elems = (size_t)ceil_div(nc, 32) * p.m_pad * 32;
+    // fp16 product: column maxima and scales (floats) follow the split V in the lo part
+    *vlo_elems = *vsplit_elems + (p.f16v ? 2 * (size_t)(VMAX_BLOCKS + 2) * m : 0);
+  } else if (p.path == 1 && prec == NYS_FP64 && p.waves == 8) {
+    *vsplit_elems = 4 * (size_t)ceil_div(nc, 32) * p.m_pad * 32;   // permuted V, doubles as 4 u16
+  }
 }
 
 void kmv_reserve(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec, Arena &ws,
                  void **partial, void **vhi, void **vlo) {
-  size_t pb, ve;
-  kmv_scratch_sizes(p, nr, nc, m, prec, &pb, &ve);
+  size_t pb, ve, vl;
+  kmv_scratch_sizes(p, nr, nc, m, prec, &pb, &ve, &vl);
   *partial = nullptr;
   *vhi = *vlo = nullptr;
   if (pb) *partial = ws.take<char>(pb);
-  if (ve) {
-    *vhi = ws.take<u16>(ve);
-    *vlo = ws.take<u16>(ve);
-  }
+  if (ve) *vhi = ws.take<u16>(ve);
+  if (vl) *vlo = ws.take<u16>(vl);
 }
 
 static int ksmax_for(int prec, int Kp) {
@@ -465,6 +493,14 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, c
       a.V2 = vlo;
       a.vscale = iscale;
       a.m_pad = plan.m_pad;
+    } else if (prec == NYS_FP64 && plan.waves == 8) {
+      const int64_t total = ceil_div(cols.n, 32) * 32 * plan.m_pad;
+      hipLaunchKernelGGL(vperm64_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s,
+                         reinterpret_cast<const double *>(V), ldv, cols.n, m, plan.tm, chunks, total,
+                         reinterpret_cast<double *>(vhi));
+      NYS_LAUNCH_CHECK();
+      a.V = vhi;
+      a.m_pad = plan.m_pad;
     } else if (prec == NYS_BF16X3) {
       const int64_t nblk = ceil_div(cols.n, 32);
       const int64_t total = nblk * plan.m_pad * 32;
@@ -487,7 +523,8 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, c
   }
   dim3 grid((unsigned)nb_pad);
   int32_t rc;
-  if (prec == NYS_FP64) rc = kmv_dispatch_f64(plan, k.kind, deriv, ksmax, a, grid, s);
+  if (prec == NYS_FP64 && plan.path == 1 && plan.waves == 8) rc = kmv_dispatch_f64p(plan, k.kind, deriv, ksmax, a, grid, s);
+  else if (prec == NYS_FP64) rc = kmv_dispatch_f64(plan, k.kind, deriv, ksmax, a, grid, s);
   else if (prec == NYS_FP32) rc = kmv_dispatch_f32(plan, k.kind, deriv, ksmax, a, grid, s);
   else if (plan.path == 1 && plan.f16v) rc = kmv_dispatch_f16(plan, k.kind, deriv, ksmax, a, grid, s);
   else rc = kmv_dispatch_bf16(plan, k.kind, deriv, ksmax, a, grid, s);

@@ -580,6 +580,205 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
       }
 }
 
+// ===================================================================== flash, pipelined (FP64)
+// The float64 product (the refinement residual) on the same eight-wave schedule as
+// the BF16X3 tile: 256 rows per workgroup, 32-point column tiles double buffered in
+// LDS, V streamed global-to-LDS while the previous tile computes.  V arrives
+// permuted (vperm64_kernel) so that the B operand of the 16x16x4 float64 MFMA is 64
+// consecutive doubles per lane group read: for tile rows j = 16 h + 4 v + g and a
+// 16-column block cb, element (j, c) sits at [h][v][cb][g][c % 16].  The exponent
+// MFMA leaves K[i][16 h + g + 4 v] in lane (g, i), which is exactly the A operand of
+// MFMA v of half h.  Per tile and wave: 2 R KS MFMAs for the exponents, 8 R TM/16 for
+// K V, 8 R float64 exponentials per lane.
+template <int KIND, int KSMAX, int TM>
+__global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
+  constexpr int R = 2, WAVES = KMV2_THREADS / 64;
+  constexpr int TJ = 32, TI = WAVES * R * 16, NCB = TM / 16;
+  constexpr int VCH = TJ * TM / 2;                 // 16-byte chunks of V per tile
+  typedef __attribute__((address_space(3))) void lds_void;
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int strideA = a.Kp + 2;                    // doubles; 4 (2 Kp / 4 + 1) dwords: conflict-free rows
+  const size_t a_bytes = ((size_t)TJ * strideA * 8 + 15) & ~size_t(15);
+  double *const sA0 = reinterpret_cast<double *>(smem);
+  double *const sA1 = reinterpret_cast<double *>(smem + a_bytes);
+  double *const sV0 = reinterpret_cast<double *>(smem + 2 * a_bytes);
+  double *const sV1 = sV0 + TJ * TM;
+
+  const int64_t ntiles = (a.nr + TI - 1) / TI;
+  const int64_t nb = ntiles * a.chunks * a.nsplit;
+  const int64_t nb_pad = (nb + 7) / 8 * 8;
+  const int64_t lid = xcd_logical_block(nb_pad);
+  if (lid >= nb) return;
+  const int64_t tile = lid % ntiles;
+  const int64_t rest = lid / ntiles;
+  const int chunk = (int)(rest % a.chunks);
+  const int split = (int)(rest / a.chunks);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col16 = lane & 15, grp = lane >> 4;
+  const int ks = a.Kp / 4;
+  const int64_t i0 = tile * TI;
+  const int64_t iw = i0 + (int64_t)wave * R * 16;
+  const int c0 = chunk * TM;
+  const double *Ag = reinterpret_cast<const double *>(a.Acols);
+  const double *Bg = reinterpret_cast<const double *>(a.Brows);
+  const double *Vp = reinterpret_cast<const double *>(a.V);
+
+  double bop[R][KSMAX];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) bop[r][s] = (s < ks) ? Bg[(iw + r * 16 + col16) * a.Kp + s * 4 + grp] : 0.0;
+
+  d4 acc[R][NCB];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = d4{0, 0, 0, 0};
+
+  const double cL = a.cL, dcoef = a.dcoef;
+  const int64_t njt = (a.nc + TJ - 1) / TJ;
+  const int64_t jt0 = (int64_t)split * a.jsteps;
+  const int64_t jt1 = jt0 + a.jsteps < njt ? jt0 + a.jsteps : njt;
+
+  // packed points of one tile: TJ rows x Kp doubles = 16 Kp chunks of 16 bytes
+  const int cpr = a.Kp / 2;
+  const int achunks = TJ * cpr;
+  constexpr int APRE = (KSMAX * 4 * TJ / 2 + KMV2_THREADS - 1) / KMV2_THREADS;
+  static_assert(APRE <= 2, "point prefetch holds at most two chunks per thread");
+  uint4 apre0 = {0, 0, 0, 0}, apre1 = {0, 0, 0, 0};
+  auto load_points = [&](int64_t jt) {
+    const uint4 *g = reinterpret_cast<const uint4 *>(Ag + jt * TJ * a.Kp);
+    apre0 = g[tid < achunks ? tid : achunks - 1];
+    if constexpr (APRE > 1) {
+      const int c = tid + KMV2_THREADS;
+      apre1 = g[c < achunks ? c : achunks - 1];
+    }
+  };
+  auto store_points = [&](double *dst) {
+    if (tid < achunks) {
+      const int r = tid / cpr, o = tid - r * cpr;
+      *reinterpret_cast<uint4 *>(dst + r * strideA + o * 2) = apre0;
+    }
+    if constexpr (APRE > 1) {
+      const int c = tid + KMV2_THREADS;
+      if (c < achunks) {
+        const int r = c / cpr, o = c - r * cpr;
+        *reinterpret_cast<uint4 *>(dst + r * strideA + o * 2) = apre1;
+      }
+    }
+  };
+  // permuted V of one tile: TJ x TM doubles, contiguous; copied in 1 KB wave blocks
+  auto stream_v = [&](int64_t jt, double *dst) {
+    const double *g = Vp + (jt * a.chunks + chunk) * (TJ * TM);
+#pragma unroll
+    for (int k = 0; k < (VCH + KMV2_THREADS - 1) / KMV2_THREADS; ++k) {
+      const int blk = k * KMV2_THREADS + wave * 64;          // wave-uniform
+      if (blk < VCH) {
+        const int q = blk + lane;
+        __builtin_amdgcn_global_load_lds(g + q * 2, (lds_void *)(dst + blk * 2), 16, 0, 0);
+      }
+    }
+  };
+
+  if (jt0 < jt1) {
+    load_points(jt0);
+    stream_v(jt0, sV0);
+    store_points(sA0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  for (int64_t jt = jt0; jt < jt1; ++jt) {
+    const int cur = (int)((jt - jt0) & 1);
+    const double *sAc = cur ? sA1 : sA0;
+    const double *sVc = cur ? sV1 : sV0;
+    const bool more = jt + 1 < jt1;
+    if (more) {
+      stream_v(jt + 1, cur ? sV0 : sV1);
+      load_points(jt + 1);
+    }
+    const int64_t j0 = jt * TJ;
+    const bool diag = a.same && (j0 < i0 + TI) && (i0 < j0 + TJ);
+
+    // exponents: rows j of the tile (two halves of 16) against the R row blocks
+    d4 ta[R], tb[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ta[r] = tb[r] = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s)
+      if (s < ks) {
+        const double a0 = sAc[col16 * strideA + s * 4 + grp];
+        const double a1 = sAc[(16 + col16) * strideA + s * 4 + grp];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ta[r] = mfma16(a0, bop[r][s], ta[r]);
+          tb[r] = mfma16(a1, bop[r][s], tb[r]);
+        }
+      }
+    // kernel values: lane (g, i) holds K[i][g + 4 v] (half 0) and K[i][16 + g + 4 v]
+    double ka[R][4], kb[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t gi = iw + r * 16 + col16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t1 = ta[r][v], t2 = tb[r][v];
+        if (diag && gi == j0 + grp + 4 * v) t1 = 0.0;
+        if (diag && gi == j0 + 16 + grp + 4 * v) t2 = 0.0;
+        ka[r][v] = kernel_value<NYS_FP64, KIND, 0>(t1, cL, dcoef);
+        kb[r][v] = kernel_value<NYS_FP64, KIND, 0>(t2, cL, dcoef);
+      }
+    }
+    // K V: MFMA v of half h contracts j = 16 h + 4 v + g
+    const double *vl = sVc + lane;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double b0 = vl[((0 * 4 + v) * NCB + cb) * 64];
+        const double b1 = vl[((1 * 4 + v) * NCB + cb) * 64];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          acc[r][cb] = mfma16(ka[r][v], b0, acc[r][cb]);
+          acc[r][cb] = mfma16(kb[r][v], b1, acc[r][cb]);
+        }
+      }
+    }
+    if (more) store_points(cur ? sA0 : sA1);
+    __builtin_amdgcn_s_waitcnt(0);   // the streamed tile has landed
+    __syncthreads();
+  }
+
+  double *O = reinterpret_cast<double *>(a.Out);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = iw + r * 16 + out_row<NYS_FP64>(grp, v);
+        const int c = c0 + cb * 16 + col16;
+        if (i < a.nr && c < a.m) {
+          const double sum = acc[r][cb][v];
+          if (a.partial) {
+            O[((int64_t)split * a.nr + i) * a.m + c] = sum;
+          } else {
+            double val = a.alpha * sum;
+            if (a.beta != 0.0) val += a.beta * O[i * a.ldo + c];
+            O[i * a.ldo + c] = val;
+          }
+        }
+      }
+}
+
+template <int TM>
+inline size_t kmv_flash64_lds(int Kp) {
+  const size_t a = ((size_t)32 * (Kp + 2) * 8 + 15) & ~size_t(15);
+  return 2 * a + (size_t)2 * 32 * TM * 8;
+}
+
 template <int TM>
 inline size_t kmv_flash2_lds(int Kp) {
   const size_t a = ((size_t)32 * lds_stride<NYS_BF16X3>(Kp) * 2 + 15) & ~size_t(15);
@@ -610,6 +809,8 @@ int32_t kmv_dispatch_f32(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs
 int32_t kmv_dispatch_bf16(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
                           hipStream_t s);
 int32_t kmv_dispatch_f16(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
+                          hipStream_t s);
+int32_t kmv_dispatch_f64p(const KmvPlan &p, int kind, int deriv, int ksmax, KArgs &a, dim3 grid,
                           hipStream_t s);
 
 }  // namespace nys

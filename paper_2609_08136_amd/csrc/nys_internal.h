@@ -124,9 +124,10 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp);
 // Scratch needed by kmv_run for a plan (partials, split V).
 void kmv_reserve(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec, Arena &ws,
                  void **partial, void **vhi, void **vlo);
-// Bytes of partial sums and elements of each split-V part a plan needs.
+// Bytes of partial sums and u16 elements of the two split-V parts (hi, lo) a plan
+// needs (the float64 tile keeps its permuted V in the hi part).
 void kmv_scratch_sizes(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec,
-                       size_t *partial_bytes, size_t *vsplit_elems);
+                       size_t *partial_bytes, size_t *vsplit_elems, size_t *vlo_elems);
 
 // Out = alpha * K V + beta * Out using packed points.  V/Out are double for
 // FP64 else float.  same_points marks A == B point sets (K_ii = 1 exactly).

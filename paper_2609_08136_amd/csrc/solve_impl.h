@@ -240,9 +240,10 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
       } else {
         thr[q] = tol;
       }
-      // a recursion whose residual grew 10x above its best of the cycle has lost
-      // its footing: refine (and restart) it now
-      const bool diverging = refine && rel[q] > 10.0 * c.rmin && rel[q] > tol;
+      // a recursion whose residual grew 100x above its best of the cycle and 10x above
+      // the residual the cycle started from has lost its footing: refine (and restart)
+      // it now.  (CG residuals are not monotone: smaller excursions are normal.)
+      const bool diverging = refine && rel[q] > 100.0 * c.rmin && rel[q] > 10.0 * c.rstart && rel[q] > tol;
       c.rmin = std::min(c.rmin, rel[q]);
       dv[q] = diverging;
       if (diverging) thr[q] = rel[q];
