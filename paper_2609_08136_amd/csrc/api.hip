@@ -86,8 +86,9 @@ void plan_kmv(KmvBufs &b, int64_t nr, int64_t nc, int d, int m_lo, int m_max, in
     vl = std::max(vl, l);
   }
   // the derivative product runs in chunks of <= 4 columns with the 4-column plan
-  const KmvPlan p4 = kmv_plan(nr, nc, 4, prec, b.rows.Kp);
-  kmv_scratch_sizes(p4, nr, nc, std::min(4, std::max(1, m_max)), prec, &a, &e, &l);
+  // (row-sum tile: planned with the distance packing's precision, no fp16 product)
+  const KmvPlan p4 = kmv_plan(nr, nc, 4, packing_prec(prec), b.rows.Kp);
+  kmv_scratch_sizes(p4, nr, nc, std::min(4, std::max(1, m_max)), packing_prec(prec), &a, &e, &l);
   pb = std::max(pb, a);
   b.partial = pb ? ws.take<char>(pb) : nullptr;
   b.vhi = ve ? ws.take<bf16bits>(ve) : nullptr;
@@ -107,8 +108,9 @@ int32_t run_kmv(KmvBufs &b, const nys_kernel &k, int deriv, int prec, int same, 
                 int ldv, void *Out, int ldo, double alpha, double beta, hipStream_t s) {
   if (m <= 0) return NYS_OK;
   const size_t eb = elem_bytes(prec);
-  if (deriv && m > 1) {
-    const KmvPlan p = kmv_plan(b.rows.n, b.cols.n, 4, prec, b.rows.Kp);
+  if (deriv) {
+    // the derivative runs on the row-sum tile in chunks of <= 4 columns
+    const KmvPlan p = kmv_plan(b.rows.n, b.cols.n, m == 1 ? 1 : 4, packing_prec(prec), b.rows.Kp);
     for (int c0 = 0; c0 < m; c0 += 4) {
       const int mc = std::min(4, m - c0);
       NYS_RETURN_IF(kmv_run(p, k, 1, prec, b.rows, b.cols, same,

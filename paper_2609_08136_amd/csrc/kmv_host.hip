@@ -333,8 +333,9 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   const bool f16v = f16_product(prec);
   prec = kernel_prec(prec);
   KmvPlan p;
-  // float64: the pipelined tile beats the row-sum tile from 5 columns on (16-column chunks)
-  const int mm_cap = prec == NYS_FP64 ? 4 : 16;
+  // float64: the pipelined tile beats the row-sum tile from 5 columns on (16-column
+  // chunks); the fp16-product tile (16-column chunk) beats it at every width
+  const int mm_cap = prec == NYS_FP64 ? 4 : (f16v ? 0 : 16);
   Override ov;
   {
     std::lock_guard<std::mutex> lk(g_ovr_mu);
@@ -348,7 +349,7 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   } else {
     p.path = 1;
     if (prec == NYS_BF16X3) {
-      p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : (m <= 128 ? 128 : 256));
+      p.tm = m <= 32 ? (f16v && m <= 16 ? 16 : 32) : (m <= 64 ? 64 : (m <= 128 ? 128 : 256));
       p.r = 2;
     } else if (prec == NYS_FP32) {
       p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : 64);   // 128 would exceed the float64 tile's registers
