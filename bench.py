@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--prec", default="f16x3_d10", choices=["bf16x3", "bf16x3_d6", "bf16x3_d10", "f16x3_d10"],
                     help="kernel-product precision of the batched workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the tile autotuner (heuristic chunk widths)")
+    ap.add_argument("--tile-cache", default=os.path.expanduser("~/.cache/paper_2609_08136_amd/tiles.json"),
+                    help="JSON cache of autotuned chunk widths")
     ap.add_argument("--workload", default="batched_lambda_grid",
                     choices=["batched_lambda_grid", "plain_fp64", "matrix_free_fp32", "precision_variant",
                              "differentiation"],
@@ -341,6 +345,13 @@ def main():
     Om = torch.empty_like(Omega0)
     log(args, f"inputs ready: n={n} d={d} r={r} columns={m}")
 
+    t_tune = 0.0
+    tiles = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tiles = nys.autotune(X, w.kind, w.sigma, prec, m, cache=args.tile_cache, n_rows=min(n, 262144))
+        t_tune = time.perf_counter() - t0
+        log(args, f"autotune ({t_tune:.1f} s): " + ", ".join(f"{k}: {v['tm']}" for k, v in tiles.items()))
     if args.kmv_only and args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
         dst = torch.empty_like(src)
@@ -433,6 +444,7 @@ def main():
             "precision": f"{args.prec} K V, fp32 CG, fp64 residual refinement",
             "refine_every": args.refine_every, "refine_mode": args.refine_mode,
         },
+        "tiles": {"autotune_s": round(t_tune, 1), "widths": {k: v["tm"] for k, v in (tiles or {}).items()}},
         "kernel_matvec_tflops": round(kmv_tflops, 1),
         "kernel_matvec": {"m": m, "ms": round(t_kmv * 1e3, 2), "tflops": round(kmv_tflops, 1),
                           "m1_ms": round(t_kmv1 * 1e3, 2),

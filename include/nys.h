@@ -93,7 +93,8 @@ typedef enum {
   NYS_OP_PRECOND_BUILD = 2,
   NYS_OP_PRECOND_APPLY = 3,
   NYS_OP_SOLVE = 4,
-  NYS_OP_BACKWARD = 5
+  NYS_OP_BACKWARD = 5,
+  NYS_OP_AUTOTUNE = 6
 } nys_op;
 
 /* Kernel function: kind (nys_kind) and bandwidth sigma > 0. */
@@ -189,6 +190,7 @@ typedef struct {
  *   PRECOND_APPLY: n, r, m, prec
  *   SOLVE:         n, d, r (0 if no preconditioner), m = nlam * nrhs, prec
  *   BACKWARD:      n, d, r, prec
+ *   AUTOTUNE:      n = n_rows, n2 = n, d, m, prec
  * Returns NYS_OK and *bytes, or NYS_EINVAL. */
 int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_t r, int32_t m,
                             int32_t prec, size_t *bytes);
@@ -280,6 +282,33 @@ int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, dou
                         void *stream);
 
 /* Thread-local description of the last non-zero status ("" if none). */
+/* ---- tile autotuner -------------------------------------------------------
+ * The batched solve runs the kernel product at many column counts (columns
+ * leave as they converge).  nys_autotune times kernel_matvec(X[0:n_rows], X)
+ * on the calling stream for every candidate column-chunk width of the tile the
+ * precision uses at m columns (the instantiated widths 16..256 with at most 4
+ * chunks and at most twice the next power of two of m), reps timed calls each
+ * after one untimed call, and records the fastest for column counts in
+ * [m_lo, m] of this precision; later plans (kernel_matvec, nys_sketch,
+ * nyspcg_solve, nyspcg_backward, nys_workspace_bytes) use it.  best gets the
+ * width and its average milliseconds ({0, 0, 0} when m runs on the row-sum
+ * tile, which has no width to choose).  Synchronizes the stream.  The
+ * choice is process-wide; query workspace sizes after tuning.  X is n x d
+ * float64 (device), ws at least nys_workspace_bytes(NYS_OP_AUTOTUNE, n_rows, n,
+ * d, 0, m, prec).  nys_set_tile installs a width (e.g. from a cache of earlier
+ * runs; tm = 0 removes the range) and nys_clear_tiles drops every choice. */
+typedef struct {
+  int32_t tm;        /* column-chunk width */
+  int32_t reserved;
+  double ms;         /* average duration of one product at that width */
+} nys_tile_choice;
+
+int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int64_t n_rows, int32_t d,
+                     int32_t m, int32_t m_lo, int32_t reps, nys_tile_choice *best, void *ws, size_t ws_bytes,
+                     void *stream);
+int32_t nys_set_tile(int32_t prec, int32_t m_lo, int32_t m_hi, int32_t tm);
+void nys_clear_tiles(void);
+
 const char *nys_last_error(void);
 
 /* Library version string. */

@@ -24,10 +24,11 @@ PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16X3_D6: "bf16x3_d
 PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
-OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BACKWARD = range(6)
+OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BACKWARD, OP_AUTOTUNE = range(7)
 
 EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "nys_sketch", "nys_precond_build",
-           "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_last_error", "nys_version")
+           "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_autotune", "nys_set_tile",
+           "nys_clear_tiles", "nys_last_error", "nys_version")
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -50,6 +51,10 @@ class NysPCGOpts(ctypes.Structure):
 class NysColInfo(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("refinements", c_i32), ("status", c_i32), ("reserved", c_i32),
                 ("relres_recursive", c_f64), ("relres_true", c_f64)]
+
+
+class NysTileChoice(ctypes.Structure):
+    _fields_ = [("tm", c_i32), ("reserved", c_i32), ("ms", c_f64)]
 
 
 class NysError(RuntimeError):
@@ -84,8 +89,13 @@ def load(path: str | None = None):
     lib.nyspcg_backward.argtypes = [NysKernel, c_vp, c_i64, c_i32, c_f64, c_vp, c_vp, ctypes.POINTER(NysPrecondC),
                                     ctypes.POINTER(NysPCGOpts), c_vp, ctypes.POINTER(c_f64), ctypes.POINTER(c_f64),
                                     ctypes.POINTER(NysColInfo), c_vp, c_sz, c_vp]
+    lib.nys_autotune.argtypes = [NysKernel, c_i32, c_vp, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32,
+                                 ctypes.POINTER(NysTileChoice), c_vp, c_sz, c_vp]
+    lib.nys_set_tile.argtypes = [c_i32, c_i32, c_i32, c_i32]
+    lib.nys_clear_tiles.argtypes = []
+    lib.nys_clear_tiles.restype = None
     for name in ("kernel_matvec", "nys_sketch", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
-                 "nyspcg_backward", "nys_workspace_bytes"):
+                 "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -309,3 +319,72 @@ def build_preconditioner(X, Omega, kind: int, sigma: float, sketch_prec: int = F
     P = nys_precond_build(Y, Omega, sketch_prec, with_fp32)
     del Y
     return P
+
+
+# ------------------------------------------------------------------------------ autotuner
+# Column-count buckets of the batched solve: the product is tuned at each bucket's
+# upper end and the choice serves the whole bucket.
+TUNE_BUCKETS = ((1, 16), (17, 32), (33, 64), (65, 128), (129, 256), (257, 512), (513, 1024))
+
+
+def nys_autotune(X, kind: int, sigma: float, prec: int, m: int, m_lo: int | None = None, n_rows: int | None = None,
+                 reps: int = 1) -> tuple[int, float]:
+    """Time the candidate chunk widths of the product at m columns (rows X[0:n_rows]
+    against all of X) and record the fastest for column counts [m_lo, m].
+    Returns (width, ms); width 0 when m runs on the row-sum tile."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    n, d = X.shape
+    n_rows = n if n_rows is None else int(n_rows)
+    m_lo = m if m_lo is None else int(m_lo)
+    ws = _workspace(nys_workspace_bytes(OP_AUTOTUNE, n_rows, n, d, 0, m, prec), X.device)
+    best = NysTileChoice()
+    _check(lib.nys_autotune(NysKernel(kind, 0, float(sigma)), prec, X.data_ptr(), n, n_rows, d, m, m_lo, reps,
+                            ctypes.byref(best), ws.data_ptr(), ws.numel(), _stream()))
+    return int(best.tm), float(best.ms)
+
+
+def nys_set_tile(prec: int, m_lo: int, m_hi: int, tm: int) -> None:
+    _check(load().nys_set_tile(prec, m_lo, m_hi, tm))
+
+
+def nys_clear_tiles() -> None:
+    load().nys_clear_tiles()
+
+
+def autotune(X, kind: int, sigma: float, prec: int, m_max: int, cache: str | None = None, reps: int = 1,
+             n_rows: int | None = None) -> dict:
+    """Tune every column-count bucket up to m_max (see TUNE_BUCKETS), timing rows
+    X[0:n_rows] against all of X (the chunk width is a property of the tile, so a
+    row subsample keeps the tuning short).  With `cache`
+    (a JSON file), choices recorded for the same device, precision, kernel and point
+    set shape are installed instead of re-timed, and new ones are added to it."""
+    import json
+    n_rows = X.shape[0] if n_rows is None else min(int(n_rows), X.shape[0])
+    key = f"{torch.cuda.get_device_name(X.device)}|prec{prec}|kind{kind}|n{X.shape[0]}|d{X.shape[1]}|rows{n_rows}"
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+    entries = table.get(key, {})
+    out = {}
+    for lo, hi in TUNE_BUCKETS:
+        if lo > m_max:
+            break
+        tag = f"{lo}-{hi}"
+        if tag in entries:
+            tm = int(entries[tag]["tm"])
+            if tm:
+                nys_set_tile(prec, lo, hi, tm)
+            out[tag] = entries[tag]
+            continue
+        tm, ms = nys_autotune(X, kind, sigma, prec, min(hi, m_max), m_lo=lo, n_rows=n_rows, reps=reps)
+        if tm and hi > m_max:
+            nys_set_tile(prec, lo, hi, tm)
+        out[tag] = entries[tag] = {"tm": tm, "ms": ms}
+    if cache:
+        table[key] = entries
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as f:
+            json.dump(table, f, indent=1)
+    return out

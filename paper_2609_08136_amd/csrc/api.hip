@@ -129,9 +129,56 @@ int32_t run_kmv(KmvBufs &b, const nys_kernel &k, int deriv, int prec, int same, 
 struct MatvecPlan {
   KmvBufs kv;
 };
+
+// Autotuner buffers: V (n x m), Out (n_rows x m) and the kernel-product scratch of
+// the largest candidate chunk width.  The candidates are the instantiated widths
+// of the precision with at most 4 chunks and at most twice the next power of two
+// of m (none when m runs on the row-sum tile).
+struct AutotunePlan {
+  KmvBufs kv;
+  void *V = nullptr, *Out = nullptr;
+  std::vector<int> cands;
+};
 void plan_matvec(MatvecPlan &p, int64_t nr, int64_t nc, int d, int m, int prec, Arena &ws) {
   // the derivative product runs in chunks of <= 4 columns: reserve for both
   plan_kmv(p.kv, nr, nc, d, std::min(m, 4), m, prec, ws);
+}
+
+int32_t plan_autotune(AutotunePlan &p, int64_t n_rows, int64_t n, int d, int m, int prec, Arena &ws) {
+  const int key = f16_product(prec) ? NYS_F16X3_D10 : kernel_prec(prec);
+  p.cands.clear();
+  const int base = kmv_plan(n_rows, n, m, prec, packed_kp(d, prec)).path;
+  if (base == 1) {
+    int pw = 1;
+    while (pw < m) pw *= 2;
+    for (int tm : {16, 32, 64, 128, 256})
+      if (kmv_tile_valid(key, tm) && ceil_div(m, tm) <= 4 && tm <= 2 * std::max(pw, 16)) p.cands.push_back(tm);
+  }
+  const size_t eb = elem_bytes(prec);
+  p.V = ws.take<char>((size_t)n * m * eb);
+  p.Out = ws.take<char>((size_t)n_rows * m * eb);
+  // points packed once; scratch for the largest candidate (the table is restored after)
+  p.kv.mu = ws.take<double>(d);
+  p.kv.mpart = ws.take<double>(col_mean_partial_elems(n, d));
+  plan_points(p.kv.rows, n_rows, d, prec, ws);
+  plan_points(p.kv.cols, n, d, prec, ws);
+  size_t pb = 0, ve = 0, vl = 0, a = 0, e = 0, l = 0;
+  std::vector<int> widths = p.cands;
+  if (widths.empty()) widths.push_back(0);
+  const auto saved = kmv_tune_snapshot();
+  for (int tm : widths) {
+    if (tm) kmv_tune_set(key, m, m, tm);
+    const KmvPlan kp = kmv_plan(n_rows, n, m, prec, p.kv.rows.Kp);
+    kmv_scratch_sizes(kp, n_rows, n, m, prec, &a, &e, &l);
+    pb = std::max(pb, a);
+    ve = std::max(ve, e);
+    vl = std::max(vl, l);
+  }
+  kmv_tune_restore(saved);
+  p.kv.partial = pb ? ws.take<char>(pb) : nullptr;
+  p.kv.vhi = ve ? ws.take<bf16bits>(ve) : nullptr;
+  p.kv.vlo = vl ? ws.take<bf16bits>(vl) : nullptr;
+  return NYS_OK;
 }
 
 // ------------------------------------------------------------ sketch
@@ -336,10 +383,88 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
       plan_deriv(q, std::max<int64_t>(n, 1), std::max(d, 1), a);
       break;
     }
+    case NYS_OP_AUTOTUNE: {
+      AutotunePlan p;
+      NYS_RETURN_IF(plan_autotune(p, std::max<int64_t>(n, 1), std::max<int64_t>(n2, 1), std::max(d, 1),
+                                  std::max(m, 1), prec, a));
+      break;
+    }
     default:
       return einval("unknown op");
   }
   *bytes = a.off;
+  return NYS_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+int32_t nys_set_tile(int32_t prec, int32_t m_lo, int32_t m_hi, int32_t tm) {
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (m_lo < 1 || m_hi < m_lo) return einval("need 1 <= m_lo <= m_hi");
+  const int key = f16_product(prec) ? NYS_F16X3_D10 : kernel_prec(prec);
+  if (tm != 0 && !kmv_tile_valid(key, tm)) return einval("no tile of this width for this precision");
+  kmv_tune_set(key, m_lo, m_hi, tm);
+  return NYS_OK;
+}
+
+void nys_clear_tiles(void) { kmv_tune_clear(); }
+
+int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int64_t n_rows, int32_t d,
+                     int32_t m, int32_t m_lo, int32_t reps, nys_tile_choice *best, void *ws, size_t ws_bytes,
+                     void *stream) {
+  NYS_RETURN_IF(check_kernel(k));
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (n < 1 || n_rows < 1 || n_rows > n) return einval("need 1 <= n_rows <= n");
+  if (d < 1 || d > max_dim(prec)) return einval("d out of range for this precision");
+  if (m < 1 || m_lo < 1 || m_lo > m || reps < 1) return einval("need 1 <= m_lo <= m and reps >= 1");
+  if (!X || !best || !ws) return einval("null pointer");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  AutotunePlan p;
+  NYS_RETURN_IF(plan_autotune(p, n_rows, n, d, m, prec, a));
+  NYS_RETURN_IF(check_ws(a));
+  *best = nys_tile_choice{0, 0, 0.0};
+  if (p.cands.empty()) return NYS_OK;   // the row-sum tile: nothing to choose
+  const int key = f16_product(prec) ? NYS_F16X3_D10 : kernel_prec(prec);
+  const size_t eb = elem_bytes(prec);
+  if (eb == 8) NYS_RETURN_IF(launch_fill(reinterpret_cast<double *>(p.V), 1.0 / n, n * (int64_t)m, s));
+  else NYS_RETURN_IF(launch_fill_f(reinterpret_cast<float *>(p.V), 1.0f / (float)n, n * (int64_t)m, s));
+  NYS_RETURN_IF(prep_points(p.kv, k, prec, X, X, d, s));
+  hipEvent_t e0, e1;
+  NYS_CHECK_HIP(hipEventCreate(&e0));
+  NYS_CHECK_HIP(hipEventCreate(&e1));
+  double best_ms = 1e300;
+  int best_tm = 0;
+  int32_t rc = NYS_OK;
+  const auto saved = kmv_tune_snapshot();
+  for (int tm : p.cands) {
+    kmv_tune_set(key, m, m, tm);
+    rc = run_kmv(p.kv, k, 0, prec, 0, p.V, m, m, p.Out, m, 1.0, 0.0, s);   // untimed first call
+    if (rc != NYS_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = NYS_EHIP; break; }
+    for (int t = 0; t < reps && rc == NYS_OK; ++t) rc = run_kmv(p.kv, k, 0, prec, 0, p.V, m, m, p.Out, m, 1.0, 0.0, s);
+    if (rc != NYS_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = NYS_EHIP;
+      break;
+    }
+    if (ms / reps < best_ms) {
+      best_ms = ms / reps;
+      best_tm = tm;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  kmv_tune_restore(saved);
+  if (rc == NYS_OK) kmv_tune_set(key, m_lo, m, best_tm);
+  if (rc != NYS_OK) {
+    if (rc == NYS_EHIP) set_error("nys_autotune: HIP event failure while timing");
+    return rc;
+  }
+  *best = nys_tile_choice{best_tm, 0, best_ms};
   return NYS_OK;
 }
 

@@ -242,6 +242,10 @@ __global__ void fill_kernel(double *y, double v, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) y[i] = v;
 }
+__global__ void fill_f_kernel(float *y, float v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] = v;
+}
 
 int32_t launch_axpy(double a, const double *x, double *y, int64_t count, hipStream_t s) {
   if (count <= 0) return NYS_OK;
@@ -264,6 +268,12 @@ int32_t launch_copy_f2d(const float *x, double *y, int64_t count, hipStream_t s)
 int32_t launch_fill(double *y, double v, int64_t count, hipStream_t s) {
   if (count <= 0) return NYS_OK;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, y, v, count);
+  NYS_LAUNCH_CHECK();
+  return NYS_OK;
+}
+int32_t launch_fill_f(float *y, float v, int64_t count, hipStream_t s) {
+  if (count <= 0) return NYS_OK;
+  hipLaunchKernelGGL(fill_f_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s, y, v, count);
   NYS_LAUNCH_CHECK();
   return NYS_OK;
 }

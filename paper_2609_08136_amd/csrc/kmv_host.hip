@@ -323,6 +323,54 @@ void kmv_clear_override() {
   for (auto &o : g_ovr) o = Override{};
 }
 
+// Tile widths chosen by the autotuner (nys_autotune / nys_set_tile), per original
+// precision and column-count range.  kmv_plan takes the chunk width from here.
+namespace {
+std::mutex g_tune_mu;
+struct Tuned {
+  int prec, m_lo, m_hi, tm;
+};
+std::vector<Tuned> g_tuned;
+}  // namespace
+
+bool kmv_tile_valid(int prec, int tm) {
+  switch (prec) {
+    case NYS_FP64: return tm == 16 || tm == 32 || tm == 64;
+    case NYS_FP32: return tm == 32 || tm == 64 || tm == 128;
+    case NYS_F16X3_D10: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
+    default: return tm == 32 || tm == 64 || tm == 128 || tm == 256;
+  }
+}
+void kmv_tune_set(int prec, int m_lo, int m_hi, int tm) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::vector<Tuned> keep;
+  for (const Tuned &t : g_tuned)
+    if (t.prec != prec || t.m_hi < m_lo || t.m_lo > m_hi) keep.push_back(t);
+  if (tm > 0) keep.push_back(Tuned{prec, m_lo, m_hi, tm});
+  g_tuned.swap(keep);
+}
+void kmv_tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
+}
+std::vector<std::array<int, 4>> kmv_tune_snapshot() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::vector<std::array<int, 4>> out;
+  for (const Tuned &t : g_tuned) out.push_back({t.prec, t.m_lo, t.m_hi, t.tm});
+  return out;
+}
+void kmv_tune_restore(const std::vector<std::array<int, 4>> &t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
+  for (const auto &e : t) g_tuned.push_back(Tuned{e[0], e[1], e[2], e[3]});
+}
+static int kmv_tune_get(int prec, int m) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const Tuned &t : g_tuned)
+    if (t.prec == prec && m >= t.m_lo && m <= t.m_hi) return t.tm;
+  return 0;
+}
+
 static int small_r_for(int prec, int mm) {
   if (prec == NYS_FP64) return mm <= 2 ? 4 : 2;
   return mm <= 4 ? 4 : 2;
@@ -331,6 +379,7 @@ static int small_r_for(int prec, int mm) {
 KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   (void)Kp;
   const bool f16v = f16_product(prec);
+  const int prec0 = prec;
   prec = kernel_prec(prec);
   KmvPlan p;
   // float64: the pipelined tile beats the row-sum tile from 5 columns on (16-column
@@ -352,12 +401,14 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.tm = m <= 32 ? (f16v && m <= 16 ? 16 : 32) : (m <= 64 ? 64 : (m <= 128 ? 128 : 256));
       p.r = 2;
     } else if (prec == NYS_FP32) {
-      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : 64);   // 128 would exceed the float64 tile's registers
+      p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : 128);
       p.r = 2;
     } else {
       p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : 64);   // 128 would exceed the float64 tile's registers
       p.r = 2;
     }
+    const int tuned = kmv_tune_get(f16v ? NYS_F16X3_D10 : prec0, m);
+    if (tuned > 0) p.tm = tuned;
     if (ov.set && ov.path == 1) {
       if (ov.tm) p.tm = ov.tm;
       if (ov.r) p.r = ov.r;

@@ -1,6 +1,9 @@
 // Internal declarations of libnys (not part of the public ABI).
 #pragma once
 
+#include <array>
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -136,9 +139,15 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec,
                 int m, int ldv, void *Out, int ldo, double alpha, double beta, void *partial,
                 void *vhi, void *vlo, hipStream_t s);
 
-// Override table for the autotuner (0 = use the heuristic).
+// Test hook: force a plan shape for a kernel precision (0 = use the heuristic).
 void kmv_set_override(int prec, int path, int tm, int r, int splits);
 void kmv_clear_override();
+// Autotuned chunk widths: tm for columns m in [m_lo, m_hi] of a precision (tm 0 removes).
+bool kmv_tile_valid(int prec, int tm);
+void kmv_tune_set(int prec, int m_lo, int m_hi, int tm);
+void kmv_tune_clear();
+std::vector<std::array<int, 4>> kmv_tune_snapshot();
+void kmv_tune_restore(const std::vector<std::array<int, 4>> &t);
 
 // ---------------------------------------------------------------- dense helpers
 // C[p x q] (+)= A^T B over rows [0, n): A n x p (lda), B n x q (ldb), row-major.
@@ -168,6 +177,7 @@ int32_t launch_axpy(double a, const double *x, double *y, int64_t count, hipStre
 int32_t launch_copy_d2f(const double *x, float *y, int64_t count, hipStream_t s);
 int32_t launch_copy_f2d(const float *x, double *y, int64_t count, hipStream_t s);
 int32_t launch_fill(double *y, double v, int64_t count, hipStream_t s);
+int32_t launch_fill_f(float *y, float v, int64_t count, hipStream_t s);
 
 // ---------------------------------------------------------------- small dense
 // In-place lower Cholesky of a symmetric r x r matrix (lower triangle used,

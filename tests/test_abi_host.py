@@ -130,3 +130,26 @@ def test_tile_sources_avoid_packed_fp32_ops():
     for f in os.listdir(csrc):
         txt = open(os.path.join(csrc, f)).read()
         assert "v_pk_fma_f32" not in txt and "v_pk_mul_f32" not in txt and "v_pk_add_f32" not in txt
+
+
+def test_autotune_argument_errors(lib):
+    k = nys.NysKernel(nys.RBF, 0, 1.0)
+    best = nys.NysTileChoice()
+    tune = lambda **kw: lib.nys_autotune(k, kw.get("prec", 0), kw.get("X", FAKE), kw.get("n", 100),
+                                         kw.get("n_rows", 100), kw.get("d", 3), kw.get("m", 8), kw.get("m_lo", 1),
+                                         kw.get("reps", 1), ctypes.byref(best), kw.get("ws", FAKE), 1 << 20, None)
+    assert tune(prec=9) == nys.EINVAL
+    assert tune(n_rows=200) == nys.EINVAL          # more rows than points
+    assert tune(m_lo=9) == nys.EINVAL              # m_lo > m
+    assert tune(reps=0) == nys.EINVAL
+    assert tune(X=None) == nys.EINVAL
+    assert tune(ws=None) == nys.EINVAL
+    assert lib.nys_set_tile(nys.FP64, 1, 64, 256) == nys.EINVAL      # no 256-wide float64 tile
+    assert lib.nys_set_tile(nys.F16X3_D10, 5, 4, 64) == nys.EINVAL   # empty range
+    assert lib.nys_set_tile(7, 1, 4, 64) == nys.EINVAL
+    assert lib.nys_set_tile(nys.F16X3_D10, 1, 64, 16) == nys.OK
+    assert lib.nys_set_tile(nys.F16X3_D10, 1, 64, 0) == nys.OK       # removes it again
+    lib.nys_clear_tiles()
+    b = ctypes.c_size_t(0)
+    assert lib.nys_workspace_bytes(6, 1000, 4000, 16, 0, 64, nys.F16X3_D10, ctypes.byref(b)) == nys.OK
+    assert b.value >= (4000 + 1000) * 64 * 4

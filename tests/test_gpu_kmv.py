@@ -212,3 +212,38 @@ def test_fp16_product_is_more_accurate(nys):
     print(f"max relative entry error: bf16 product {e_bf:.3e}, fp16 product {e_h:.3e}")
     assert e_bf < 2.0 ** -15
     assert e_h < e_bf / 8 and e_h < 2.0 ** -19
+
+
+@pytest.mark.parametrize("prec,widths", [(0, (16, 32, 64)), (1, (32, 64, 128)), (2, (32, 64, 128, 256)),
+                                         (5, (16, 32, 64, 128, 256))])
+def test_every_chunk_width_matches_oracle(nys, prec, widths):
+    """Every column-chunk width the autotuner may choose gives the same products (to
+    the precision's bound): each is forced for all column counts in turn."""
+    try:
+        for tm in widths:
+            nys.nys_set_tile(prec, 1, 1024, tm)
+            print(f"width {tm}", flush=True)
+            check(nys, 700, 700, 12, 40, o.RBF, prec, seed=tm)
+            check(nys, 300, 900, 12, 70, o.LAPLACIAN, prec, same=False, seed=tm + 1)
+    finally:
+        nys.nys_clear_tiles()
+
+
+def test_autotune_records_a_valid_width(nys):
+    rng = np.random.default_rng(5)
+    X = torch.from_numpy(rng.standard_normal((6000, 16))).to(torch.device("cuda"))
+    try:
+        tm, ms = nys.nys_autotune(X, o.RBF, 4.0, nys.F16X3_D10, 100, m_lo=65, reps=1)
+        print(f"chosen width {tm}, {ms:.3f} ms")
+        assert tm in (16, 32, 64, 128) and ms > 0
+        # the recorded width is used for 65..100 columns: products still match the oracle
+        Xn = X.cpu().numpy()
+        V = rng.standard_normal((6000, 80)).astype(np.float32).astype(np.float64)
+        got = run(nys, Xn, Xn, V, o.RBF, 4.0, 5)
+        ref = o.kernel_matvec(Xn, Xn, V, o.RBF, 4.0)
+        assert np.max(np.abs(got - ref) / bound(Xn, Xn, V, o.RBF, 4.0, 5, 0)) <= 1.0
+        t0, _ = nys.nys_autotune(X, o.RBF, 4.0, nys.F16X3_D10, 1, reps=1)   # one column: fp16 tile too
+        assert t0 in (16, 32)
+        assert nys.nys_autotune(X, o.RBF, 4.0, nys.FP64, 3, reps=1)[0] == 0  # row-sum tile: nothing to tune
+    finally:
+        nys.nys_clear_tiles()
