@@ -335,7 +335,7 @@ std::vector<Tuned> g_tuned;
 
 bool kmv_tile_valid(int prec, int tm) {
   switch (prec) {
-    case NYS_FP64: return tm == 16 || tm == 32 || tm == 64;
+    case NYS_FP64: return tm == 16 || tm == 32 || tm == 64 || tm == 128;
     case NYS_FP32: return tm == 32 || tm == 64 || tm == 128;
     case NYS_F16X3_D10: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
     default: return tm == 32 || tm == 64 || tm == 128 || tm == 256;
@@ -404,7 +404,7 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : 128);
       p.r = 2;
     } else {
-      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : 64);   // 128 would exceed the float64 tile's registers
+      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : (m <= 64 ? 64 : 128));
       p.r = 2;
     }
     const int tuned = kmv_tune_get(f16v ? NYS_F16X3_D10 : prec0, m);
