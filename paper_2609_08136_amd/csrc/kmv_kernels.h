@@ -518,15 +518,34 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
           tb[r] = mfma16(a1, bop[r][s], tb[r]);
         }
       }
+    // diagonal tiles (a wave-uniform test) pin the exponent of i == j to 0.  Hoisting the
+    // test out of the epilogue measured 5-6% faster at 64 and 256 columns, 2.6% slower
+    // at 128 and neutral below; those widths keep the per-element select.
+    constexpr bool HOIST = TM == 64 || TM == 256;
+    if (HOIST && diag) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t gi = iw + r * 16 + col16;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
+          if (gi == gj) {
+            if (e < 4) ta[r][e] = 0.0f;
+            else tb[r][e - 4] = 0.0f;
+          }
+        }
+      }
+    }
     PV phi[R], plo[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int64_t gi = iw + r * 16 + col16;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         float t = e < 4 ? ta[r][e] : tb[r][e - 4];
-        const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
-        if (diag && gi == gj) t = 0.0f;
+        if constexpr (!HOIST) {
+          const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
+          if (diag && iw + r * 16 + col16 == gj) t = 0.0f;
+        }
         const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);
         const PS h = (PS)kv;
         phi[r][e] = h;

@@ -52,14 +52,6 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
   if (sp.need64) NYS_RETURN_IF(prep_points(sp.kv64, k, NYS_FP64, Xpts, Xpts, d, s));
   KmvBufs &k64 = sp.need64 ? sp.kv64 : sp.kv;
 
-  // Columns whose lambda is at least the smallest retained Nystrom eigenvalue have a
-  // preconditioned condition number of at most 2: their drift stays near the product
-  // precision, so their first cycle aims at the tolerance directly (one refinement).
-  double lam_hat_min = -1.0;
-  if (refine && P && P->rank > 0) {
-    NYS_CHECK_HIP(hipMemcpyAsync(&lam_hat_min, P->lam_hat + (P->rank - 1), sizeof(double), hipMemcpyDeviceToHost, s));
-    NYS_CHECK_HIP(hipStreamSynchronize(s));
-  }
   std::vector<Slot> sl(mtot);
   std::vector<int> ih(mtot);
   std::vector<double> dh(mtot);
@@ -67,7 +59,7 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
     sl[c].orig = c;
     sl[c].bcol = c % nrhs;
     sl[c].lam = lambdas[c / nrhs];
-    sl[c].delta = (delta0 > 0.0 && lam_hat_min > 0.0 && sl[c].lam >= lam_hat_min) ? 1e-300 : delta0;
+    sl[c].delta = delta0;
     info[c] = nys_col_info{0, 0, NYS_NOT_CONVERGED, 0, 1.0, -1.0};
   }
   int ma = mtot;
