@@ -235,7 +235,7 @@ def test_autotune_records_a_valid_width(nys):
     try:
         tm, ms = nys.nys_autotune(X, o.RBF, 4.0, nys.F16X3_D10, 100, m_lo=65, reps=1)
         print(f"chosen width {tm}, {ms:.3f} ms")
-        assert tm in (16, 32, 64, 128) and ms > 0
+        assert tm in (32, 64, 128, 256) and ms > 0   # widths with <= 4 chunks, <= 2 x 128
         # the recorded width is used for 65..100 columns: products still match the oracle
         Xn = X.cpu().numpy()
         V = rng.standard_normal((6000, 80)).astype(np.float32).astype(np.float64)
