@@ -54,13 +54,13 @@ def test_precond_matches_oracle_fp64(nys, kind):
 
 
 def test_precond_low_precision_sketch_is_valid(nys):
-    """BF16X3 / FP32 sketches: the preconditioner stays SPD (U orthonormal, lam_hat >= 0)
-    and close to the FP64 one."""
+    """FP32 and bf16/fp16-split sketches: the preconditioner stays SPD (U orthonormal,
+    lam_hat >= 0) and close to the FP64 one."""
     w = ni.small_problem(1500, 10, seed=3, r=60)
     Om = ni.gaussian_test_matrix(w.n, w.r, 3)
     K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
     _, lho, _ = o.nystrom(lambda V: K @ V, Om)
-    for prec in (1, 2):
+    for prec in (1, 2, 3, 4, 5):
         _, P = build(nys, w.X, Om, w.kind, w.sigma, prec)
         lh = P.lam_hat.cpu().numpy()
         U = P.U.cpu().numpy()
@@ -151,15 +151,18 @@ def test_nan_rhs_is_reported(nys):
     assert e.value.code == nys.ENUMERIC
 
 
-@pytest.mark.parametrize("prec,mode", [(1, 0), (2, 0), (2, 1)])
-def test_low_precision_with_fp64_refinement_reaches_true_tolerance(nys, prec, mode):
-    """FP32 / BF16X3 products with float32 CG accept a column only on its float64
-    true residual; the result is checked against the oracle's direct solve."""
+@pytest.mark.parametrize("prec,mode,every", [(1, 0, 20), (2, 0, 20), (2, 1, 20), (5, 1, 20), (5, 1, 0),
+                                              (5, 2, 0), (3, 0, 0)])
+def test_low_precision_with_fp64_refinement_reaches_true_tolerance(nys, prec, mode, every):
+    """Low-precision products (FP32, BF16X3, D6, F16X3_D10) with float32 CG accept a
+    column only on its float64 true residual, with periodic (every 20) or cycle
+    (every 0) refinement in each restart mode; the result is checked against the
+    oracle's direct solve."""
     w = ni.small_problem(3000, 10, seed=9, lam=0.3, r=80)
     Om = ni.gaussian_test_matrix(w.n, w.r, 9)
     tX, P = build(nys, w.X, Om, w.kind, w.sigma, prec)
     x, info, rc = nys.nyspcg_solve(tX, T(w.B), w.lambdas, w.kind, w.sigma, P, tol=1e-6, prec=prec,
-                                   refine_every=20, refine_mode=mode, check_true=True)
+                                   refine_every=every, refine_mode=mode, check_true=True)
     K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
     ref = o.direct_solve(K, w.B[:, 0], w.lambdas[0])
     xs = x.cpu().numpy().reshape(-1)
@@ -182,12 +185,16 @@ def test_fp32_without_refinement_stops_on_recursive_residual(nys):
     assert info[0]["relres_true"] <= 1e-4
 
 
-def test_solve_deterministic(nys):
-    w = ni.small_problem(1200, 6, seed=11, nrhs=2, r=30)
+@pytest.mark.parametrize("prec", [0, 2, 5])
+def test_solve_deterministic(nys, prec):
+    """Bitwise repeatable solves: ordered reductions, no atomics (12 columns put the
+    float64 product on its pipelined tile)."""
+    w = ni.small_problem(1200, 6, seed=11, nrhs=6, r=30)
     Om = ni.gaussian_test_matrix(w.n, w.r, 11)
-    tX, P = build(nys, w.X, Om, w.kind, w.sigma, 2)
-    a, _, _ = nys.nyspcg_solve(tX, T(w.B), [0.5, 5.0], w.kind, w.sigma, P, tol=1e-6, prec=2, refine_every=20)
-    b, _, _ = nys.nyspcg_solve(tX, T(w.B), [0.5, 5.0], w.kind, w.sigma, P, tol=1e-6, prec=2, refine_every=20)
+    tX, P = build(nys, w.X, Om, w.kind, w.sigma, prec)
+    kw = dict(tol=1e-6, prec=prec) if prec == 0 else dict(tol=1e-6, prec=prec, refine_every=20)
+    a, _, _ = nys.nyspcg_solve(tX, T(w.B), [0.5, 5.0], w.kind, w.sigma, P, **kw)
+    b, _, _ = nys.nyspcg_solve(tX, T(w.B), [0.5, 5.0], w.kind, w.sigma, P, **kw)
     assert torch.equal(a, b)
 
 
@@ -240,3 +247,31 @@ def test_batched_lambda_grid_bf16x3_cycles_reach_true_tolerance(nys, prec, mode)
     refs = [info[l * 3]["refinements"] for l in range(4)]
     print(f"prec {prec} mode {mode}: iters per lambda {its} refinements {refs} worst true relres {worst:.3e}")
     assert rc == nys.OK and worst <= 1e-6
+
+
+def test_backward_low_precision_adjoint(nys):
+    """The adjoint solve on F16X3_D10 products with float64 refinement (tol 1e-9) gives
+    the dense oracle's gradient to the accuracy the tolerance allows."""
+    w = ni.small_problem(900, 6, seed=12, kind=o.RBF, r=40)
+    X, y = w.X[:750], w.B[:750, 0]
+    Xv, yv = w.X[750:], w.B[750:, 0]
+    lam, sig = 0.8, 2.0
+    L, dlam_o, dsig_o, x_o, a_o = o.validation_loss_grad(X, y, Xv, yv, o.RBF, sig, lam)
+    Om = ni.gaussian_test_matrix(750, 40, 12)
+    tX, P = build(nys, X, Om, o.RBF, sig, 5)
+    x, info, rc = nys.nyspcg_solve(tX, T(y), [lam], o.RBF, sig, P, tol=1e-9, prec=5, refine_every=0,
+                                   refine_mode=1)
+    assert rc == nys.OK
+    x = x.reshape(-1)
+    tXv = T(Xv)
+    pred = nys.kernel_matvec(tXv, tX, x, o.RBF, sig, 0)
+    e = (2.0 / len(yv)) * (pred - T(yv))
+    gx = nys.kernel_matvec(tX, tXv, e, o.RBF, sig, 0)
+    adj, dlam, dsig_impl, binfo = nys.nyspcg_backward(tX, lam, x, gx, o.RBF, sig, P, tol=1e-9, prec=5,
+                                                      refine_every=0, refine_mode=1)
+    dsig = float(torch.dot(e, nys.kernel_matvec(tXv, tX, x, o.RBF, sig, 0, deriv=1))) + dsig_impl
+    print(f"adjoint iters {binfo['iters']} refinements {binfo['refinements']}; dlam {dlam:.8e} vs {dlam_o:.8e}; "
+          f"dsig {dsig:.8e} vs {dsig_o:.8e}")
+    assert np.linalg.norm(adj.cpu().numpy() - a_o) <= 1e-6 * np.linalg.norm(a_o)
+    assert dlam == pytest.approx(dlam_o, rel=1e-5)
+    assert dsig == pytest.approx(dsig_o, rel=1e-5)
