@@ -149,6 +149,37 @@ __device__ inline typename Tr<PREC>::F kernel_value(typename Tr<PREC>::F t,
   }
 }
 
+// ------------------------------------------------------------------ float64 exp, t <= 0
+// exp(t) = 2^q 2^(j/64) e^r with k = 64 q + j = rint(64 t / ln 2) and
+// r = t - k ln2/64, |r| <= ln2/128.  ln2/64 is split into a 36-bit head (k times it
+// is exact for |k| < 2^17, so the first reduction step is exact) and a tail.
+// 2^(j/64) is read from a 64-entry table in LDS (exp_tab_init); e^r - 1 is the
+// Taylor polynomial to r^5, whose remainder r^6/720 is below 2^-54.  About one ulp
+// of error against the rounded result; arguments below -1100 return 0 (exp
+// underflows to zero below -745.2).  Twelve float64 operations and one LDS read
+// against roughly twenty for a reduction by ln 2 alone.
+__device__ inline void exp_tab_init(double *tab, int tid) {
+  if (tid < 64) tab[tid] = exp2((double)tid * (1.0 / 64.0));
+}
+__device__ inline double exp_neg_tab(double t, const double *tab) {
+  t = fmax(t, -1100.0);
+  const double kd = rint(t * 0x1.71547652b82fep+6);           // 64 / ln 2
+  const int k = (int)kd;
+  double r = fma(-kd, 0x1.62e42fefa0000p-7, t);                // head of ln2/64
+  r = fma(-kd, 0x1.cf79abc9e3b3ap-46, r);                      // tail of ln2/64
+  double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  q = fma(r, q, 1.0 / 6.0);
+  q = fma(r, q, 0.5);
+  const double p = fma(r * r, q, r);                           // e^r - 1
+  const double T = tab[k & 63];
+  return ldexp(fma(T, p, T), k >> 6);
+}
+template <int KIND>
+__device__ inline double kernel_value_tab(double t, double cL, const double *tab) {
+  if constexpr (KIND == NYS_RBF) return exp_neg_tab(t < 0.0 ? t : 0.0, tab);
+  else return exp_neg_tab(-cL * sqrt(t < 0.0 ? -t : 0.0), tab);
+}
+
 // ------------------------------------------------------------------ launch args
 struct KArgs {
   const void *Acols;   // packed column points (A operand rows j), [nc_pad][Kp]

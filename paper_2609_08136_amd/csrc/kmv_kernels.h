@@ -608,7 +608,8 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
 // 16-column block cb, element (j, c) sits at [h][v][cb][g][c % 16].  The exponent
 // MFMA leaves K[i][16 h + g + 4 v] in lane (g, i), which is exactly the A operand of
 // MFMA v of half h.  Per tile and wave: 2 R KS MFMAs for the exponents, 8 R TM/16 for
-// K V, 8 R float64 exponentials per lane.
+// K V, 8 R float64 exponentials per lane.  KSMAX below 8 is the exact number of
+// K-steps (a branch-free chain and fewer registers); 8 and 16 are upper bounds.
 template <int KIND, int KSMAX, int TM>
 __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
   constexpr int R = 2, WAVES = KMV2_THREADS / 64;
@@ -623,6 +624,7 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
   double *const sA1 = reinterpret_cast<double *>(smem + a_bytes);
   double *const sV0 = reinterpret_cast<double *>(smem + 2 * a_bytes);
   double *const sV1 = sV0 + TJ * TM;
+  double *const tab = sV1 + TJ * TM;               // 2^(j/64), j < 64
 
   const int64_t ntiles = (a.nr + TI - 1) / TI;
   const int64_t nb = ntiles * a.chunks * a.nsplit;
@@ -636,7 +638,8 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col16 = lane & 15, grp = lane >> 4;
-  const int ks = a.Kp / 4;
+  const int ks = KSMAX < 8 ? KSMAX : a.Kp / 4;
+  exp_tab_init(tab, tid);                          // visible after the first barrier
   const int64_t i0 = tile * TI;
   const int64_t iw = i0 + (int64_t)wave * R * 16;
   const int c0 = chunk * TM;
@@ -656,7 +659,7 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = d4{0, 0, 0, 0};
 
-  const double cL = a.cL, dcoef = a.dcoef;
+  const double cL = a.cL;
   const int64_t njt = (a.nc + TJ - 1) / TJ;
   const int64_t jt0 = (int64_t)split * a.jsteps;
   const int64_t jt1 = jt0 + a.jsteps < njt ? jt0 + a.jsteps : njt;
@@ -746,8 +749,8 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
         double t1 = ta[r][v], t2 = tb[r][v];
         if (diag && gi == j0 + grp + 4 * v) t1 = 0.0;
         if (diag && gi == j0 + 16 + grp + 4 * v) t2 = 0.0;
-        ka[r][v] = kernel_value<NYS_FP64, KIND, 0>(t1, cL, dcoef);
-        kb[r][v] = kernel_value<NYS_FP64, KIND, 0>(t2, cL, dcoef);
+        ka[r][v] = kernel_value_tab<KIND>(t1, cL, tab);
+        kb[r][v] = kernel_value_tab<KIND>(t2, cL, tab);
       }
     }
     // K V: MFMA v of half h contracts j = 16 h + 4 v + g
@@ -795,7 +798,7 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
 template <int TM>
 inline size_t kmv_flash64_lds(int Kp) {
   const size_t a = ((size_t)32 * (Kp + 2) * 8 + 15) & ~size_t(15);
-  return 2 * a + (size_t)2 * 32 * TM * 8;
+  return 2 * a + (size_t)2 * 32 * TM * 8 + 64 * 8;
 }
 
 template <int TM>

@@ -91,9 +91,35 @@ def test_matvec_small_m(nys, prec, kind, n, d, m):
 @pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("n,d,m", [(100, 10, 17), (1000, 16, 64), (777, 20, 50), (1500, 32, 200),
-                                   (2000, 10, 300)])
+                                   (2000, 10, 300), (600, 13, 24), (500, 5, 40)])
 def test_matvec_many_columns(nys, prec, kind, n, d, m):
     check(nys, n, n, d, m, kind, prec, seed=7 * n + m)
+
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+@pytest.mark.parametrize("m", [2, 64])
+def test_fp64_kernel_entries_over_the_whole_exponent_range(nys, kind, m):
+    """Single K entries (V = unit columns) for exponents from 0 down past the float64
+    underflow at -745: each within a few ulps plus the rounding of the exponent
+    itself; results below 1e-300 (subnormal or flushed) count as zero."""
+    n = 600
+    x = (np.arange(n, dtype=np.float64) * 0.0703125)[:, None]   # 0 .. 42.1, dyadic
+    sigma = 1.0 if kind == o.RBF else 1.0 / 20.0               # exponents down to -887 resp. -842
+    V = np.zeros((n, m))
+    cols = np.linspace(0, n - 1, m).astype(int)
+    V[cols, np.arange(m)] = 1.0
+    print(f"case exponent range kind={kind} m={m}", flush=True)
+    got = run(nys, x, x, V, kind, sigma, 0)
+    ref = o.kernel_matrix(x, x, kind, sigma)[:, cols]
+    span = (x.max() - x.mean()) ** 2 * 4
+    kap = 1.0 / (2 * sigma * sigma) if kind == o.RBF else 1.0
+    u = 2.0 ** -53
+    dt = 16 * u * (1.0 + kap * span)                           # error of the exponent
+    if kind == o.LAPLACIAN:
+        dt = 16 * u * (1.0 + span) + math.sqrt(16 * u * span) / sigma
+    tol = ref * (8 * u + dt) + 1e-300
+    assert np.all(np.abs(got - ref) <= tol), float(np.max(np.abs(got - ref) / tol))
+    assert ref.min() == 0.0 and np.all(got[ref == 0.0] <= 1e-300) and got.min() >= 0.0
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
