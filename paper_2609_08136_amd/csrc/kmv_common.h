@@ -174,10 +174,20 @@ __device__ inline double exp_neg_tab(double t, const double *tab) {
   const double T = tab[k & 63];
   return ldexp(fma(T, p, T), k >> 6);
 }
-template <int KIND>
-__device__ inline double kernel_value_tab(double t, double cL, const double *tab) {
-  if constexpr (KIND == NYS_RBF) return exp_neg_tab(t < 0.0 ? t : 0.0, tab);
-  else return exp_neg_tab(-cL * sqrt(t < 0.0 ? -t : 0.0), tab);
+// kernel_value<NYS_FP64, ...> with the table exp
+template <int KIND, int DERIV>
+__device__ inline double kernel_value_tab(double t, double cL, double dcoef, const double *tab) {
+  if constexpr (KIND == NYS_RBF) {
+    const double tt = t < 0.0 ? t : 0.0;
+    double k = exp_neg_tab(tt, tab);
+    if constexpr (DERIV) k *= (-tt) * dcoef;
+    return k;
+  } else {
+    const double dist = sqrt(t < 0.0 ? -t : 0.0);
+    double k = exp_neg_tab(-cL * dist, tab);
+    if constexpr (DERIV) k *= dist * dcoef;
+    return k;
+  }
 }
 
 // ------------------------------------------------------------------ launch args

@@ -53,6 +53,7 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_small_kernel(KArgs a) {
   E *sA = reinterpret_cast<E *>(smem);
   const size_t a_bytes = ((size_t)TJ * strideA * sizeof(E) + 15) & ~size_t(15);
   F *sV = reinterpret_cast<F *>(smem + a_bytes);
+  double *const tab = reinterpret_cast<double *>(sV + TJ * MM);   // float64: 2^(j/64), j < 64
 
   const int64_t ntiles = (a.nr + TI - 1) / TI;
   const int64_t nb = ntiles * a.nsplit;
@@ -64,8 +65,10 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_small_kernel(KArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col16 = lane & 15, grp = lane >> 4;
-  // bf16 packings are padded to exactly KSMAX K-steps, so the chain length is a constant there
-  const int ks = PREC == NYS_BF16X3 ? KSMAX : a.Kp / T::KSTEP;
+  // bf16 packings are padded to exactly KSMAX K-steps, so the chain length is a constant
+  // there; float64 tiles with KSMAX below 8 are instantiated per exact step count
+  const int ks = (PREC == NYS_BF16X3 || (PREC == NYS_FP64 && KSMAX < 8)) ? KSMAX : a.Kp / T::KSTEP;
+  if constexpr (PREC == NYS_FP64) exp_tab_init(tab, tid);   // visible after the first barrier
   const int64_t i0 = tile * TI;
   const int64_t iw = i0 + (int64_t)wave * R * 16;
   const E *Ag = reinterpret_cast<const E *>(a.Acols);
@@ -103,7 +106,10 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_small_kernel(KArgs a) {
     __syncthreads();
     const bool diag = a.same && (j0 < i0 + TI) && (i0 < j0 + TJ);
 
-#pragma unroll 2
+    // float64: one sub-block at a time keeps the exponentials' table reads within
+    // the register budget
+    constexpr int JB_UNROLL = PREC == NYS_FP64 ? 1 : 2;
+#pragma unroll JB_UNROLL
     for (int jb = 0; jb < TJ / 16; ++jb) {
       Op aop[KSMAX];
 #pragma unroll
@@ -126,7 +132,9 @@ __global__ __launch_bounds__(KMV_THREADS, 2) void kmv_small_kernel(KArgs a) {
         for (int q = 0; q < 4; ++q) {
           F tq = t[q];
           if (diag && (iw + r * 16 + col16 == j0 + jb * 16 + out_row<PREC>(grp, q))) tq = 0;
-          F kv = kernel_value<PREC, KIND, DERIV>(tq, cL, dcoef);
+          F kv;
+          if constexpr (PREC == NYS_FP64) kv = kernel_value_tab<KIND, DERIV>(tq, cL, dcoef, tab);
+          else kv = kernel_value<PREC, KIND, DERIV>(tq, cL, dcoef);
 #pragma unroll
           for (int c = 0; c < MM; ++c) acc[r][c] += kv * vv[q][c];
         }
@@ -610,8 +618,14 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
 // MFMA v of half h.  Per tile and wave: 2 R KS MFMAs for the exponents, 8 R TM/16 for
 // K V, 8 R float64 exponentials per lane.  KSMAX below 8 is the exact number of
 // K-steps (a branch-free chain and fewer registers); 8 and 16 are upper bounds.
+// Narrow tiles that fit 128 registers without spilling run four waves per SIMD (two
+// workgroups per CU).
 template <int KIND, int KSMAX, int TM>
-__global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
+constexpr int flash64_waves_per_simd() {
+  return (TM == 16 && KSMAX <= 8) || (TM == 32 && KSMAX <= 5 && KIND == NYS_RBF) ? 4 : 2;
+}
+template <int KIND, int KSMAX, int TM>
+__global__ __launch_bounds__(KMV2_THREADS, (flash64_waves_per_simd<KIND, KSMAX, TM>())) void kmv_flash64_kernel(KArgs a) {
   constexpr int R = 2, WAVES = KMV2_THREADS / 64;
   constexpr int TJ = 32, TI = WAVES * R * 16, NCB = TM / 16;
   constexpr int VCH = TJ * TM / 2;                 // 16-byte chunks of V per tile
@@ -749,8 +763,8 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash64_kernel(KArgs a) {
         double t1 = ta[r][v], t2 = tb[r][v];
         if (diag && gi == j0 + grp + 4 * v) t1 = 0.0;
         if (diag && gi == j0 + 16 + grp + 4 * v) t2 = 0.0;
-        ka[r][v] = kernel_value_tab<KIND>(t1, cL, tab);
-        kb[r][v] = kernel_value_tab<KIND>(t2, cL, tab);
+        ka[r][v] = kernel_value_tab<KIND, 0>(t1, cL, 0.0, tab);
+        kb[r][v] = kernel_value_tab<KIND, 0>(t2, cL, 0.0, tab);
       }
     }
     // K V: MFMA v of half h contracts j = 16 h + 4 v + g
@@ -812,7 +826,7 @@ template <int PREC>
 inline size_t kmv_small_lds(int Kp, int MM) {
   using T = Tr<PREC>;
   size_t a = ((size_t)64 * lds_stride<PREC>(Kp) * sizeof(typename T::E) + 15) & ~size_t(15);
-  return a + (size_t)64 * MM * sizeof(typename T::F);
+  return a + (size_t)64 * MM * sizeof(typename T::F) + (PREC == NYS_FP64 ? 64 * 8 : 0);
 }
 template <int PREC>
 inline size_t kmv_flash_lds(int Kp, int TM) {
