@@ -335,7 +335,7 @@ std::vector<Tuned> g_tuned;
 
 bool kmv_tile_valid(int prec, int tm) {
   switch (prec) {
-    case NYS_FP64: return tm == 16 || tm == 32 || tm == 64 || tm == 128;
+    case NYS_FP64: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
     case NYS_FP32: return tm == 32 || tm == 64 || tm == 128;
     case NYS_F16X3_D10: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
     default: return tm == 32 || tm == 64 || tm == 128 || tm == 256;
@@ -404,11 +404,17 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : 128);
       p.r = 2;
     } else {
-      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : (m <= 64 ? 64 : 128));
+      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : (m <= 64 ? 64 : (m <= 128 ? 128 : 256)));
       p.r = 2;
     }
     const int tuned = kmv_tune_get(f16v ? NYS_F16X3_D10 : prec0, m);
     if (tuned > 0) p.tm = tuned;
+    // float64: 64- and 256-column chunks take one 16-row block per wave (four waves
+    // per SIMD at 64 columns; 256 columns within the register budget).  Measured at
+    // n = 1e6: 64 columns 2.98 s against 3.23 s with two blocks, 256 columns 8.6 s
+    // against 9.4 s for two 128-column chunks; 128 columns are faster with two
+    // blocks (4.83 s against 5.06 s).
+    if (prec == NYS_FP64) p.r = p.tm == 64 || p.tm == 256 ? 1 : 2;
     if (ov.set && ov.path == 1) {
       if (ov.tm) p.tm = ov.tm;
       if (ov.r) p.r = ov.r;
@@ -422,7 +428,7 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.f16v = 1;
     }
     // float64 chunks run on the pipelined eight-wave float64 tile
-    if (prec == NYS_FP64 && p.r == 2) p.waves = 8;
+    if (prec == NYS_FP64) p.waves = 8;
   }
   if (p.path == 0 || p.waves != 8) {
     p.waves = 4;

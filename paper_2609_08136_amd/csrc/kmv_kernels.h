@@ -609,7 +609,8 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
 
 // ===================================================================== flash, pipelined (FP64)
 // The float64 product (the refinement residual) on the same eight-wave schedule as
-// the BF16X3 tile: 256 rows per workgroup, 32-point column tiles double buffered in
+// the BF16X3 tile: R 16-row blocks per wave (128 R rows per workgroup), 32-point
+// column tiles double buffered in
 // LDS, V streamed global-to-LDS while the previous tile computes.  V arrives
 // permuted (vperm64_kernel) so that the B operand of the 16x16x4 float64 MFMA is 64
 // consecutive doubles per lane group read: for tile rows j = 16 h + 4 v + g and a
@@ -618,15 +619,16 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
 // MFMA v of half h.  Per tile and wave: 2 R KS MFMAs for the exponents, 8 R TM/16 for
 // K V, 8 R float64 exponentials per lane.  KSMAX below 8 is the exact number of
 // K-steps (a branch-free chain and fewer registers); 8 and 16 are upper bounds.
-// Narrow tiles that fit 128 registers without spilling run four waves per SIMD (two
+// Tiles that fit 128 registers without spilling run four waves per SIMD (two
 // workgroups per CU).
-template <int KIND, int KSMAX, int TM>
+template <int KIND, int KSMAX, int TM, int R>
 constexpr int flash64_waves_per_simd() {
+  if constexpr (R == 1) return KSMAX <= 8 && TM == 64 ? 4 : 2;
   return (TM == 16 && KSMAX <= 8) || (TM == 32 && KSMAX <= 5 && KIND == NYS_RBF) ? 4 : 2;
 }
-template <int KIND, int KSMAX, int TM>
-__global__ __launch_bounds__(KMV2_THREADS, (flash64_waves_per_simd<KIND, KSMAX, TM>())) void kmv_flash64_kernel(KArgs a) {
-  constexpr int R = 2, WAVES = KMV2_THREADS / 64;
+template <int KIND, int KSMAX, int TM, int R>
+__global__ __launch_bounds__(KMV2_THREADS, (flash64_waves_per_simd<KIND, KSMAX, TM, R>())) void kmv_flash64_kernel(KArgs a) {
+  constexpr int WAVES = KMV2_THREADS / 64;
   constexpr int TJ = 32, TI = WAVES * R * 16, NCB = TM / 16;
   constexpr int VCH = TJ * TM / 2;                 // 16-byte chunks of V per tile
   typedef __attribute__((address_space(3))) void lds_void;

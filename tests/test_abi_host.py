@@ -144,7 +144,7 @@ def test_autotune_argument_errors(lib):
     assert tune(reps=0) == nys.EINVAL
     assert tune(X=None) == nys.EINVAL
     assert tune(ws=None) == nys.EINVAL
-    assert lib.nys_set_tile(nys.FP64, 1, 64, 256) == nys.EINVAL      # no 256-wide float64 tile
+    assert lib.nys_set_tile(nys.FP64, 1, 64, 512) == nys.EINVAL      # no 512-wide float64 tile
     assert lib.nys_set_tile(nys.F16X3_D10, 5, 4, 64) == nys.EINVAL   # empty range
     assert lib.nys_set_tile(7, 1, 4, 64) == nys.EINVAL
     assert lib.nys_set_tile(nys.F16X3_D10, 1, 64, 16) == nys.OK

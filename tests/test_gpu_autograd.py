@@ -35,7 +35,7 @@ def loss_and_grad(nys, ag, X, y, Xv, yv, lam, sig, kind, r=200, seed=0):
     ts = torch.tensor(math.log(sig), dtype=torch.float64, device=DEV, requires_grad=True)
     L = ag.validation_loss(tX, ty, tXv, tyv, tl, ts, kind, P, dict(tol=1e-12, prec=nys.FP64))
     L.backward()
-    return float(L), float(tl.grad), float(ts.grad)
+    return float(L.detach()), float(tl.grad), float(ts.grad)
 
 
 def test_gradient_matches_dense_oracle_and_differences(nys, subsample):
