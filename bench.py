@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kmv-only", action="store_true", help="time the kernel product only (profiling)")
+    ap.add_argument("--kmv-fp64", default="",
+                    help="with --kmv-only: also time the float64 product (the refinement residual) at these "
+                         "comma-separated column counts")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --kmv-only: first run one plain 1 GiB device copy, whose HBM counter readings "
                          "scale the kernel's (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
@@ -264,7 +267,8 @@ def time_kernel_matvec(nys, torch, X, sigma, m, prec, reps):
     """Average duration of one kernel_matvec call (HIP events on the stream it runs on)."""
     g = torch.Generator(device=X.device)
     g.manual_seed(1234)
-    V = torch.randn((X.shape[0], m), generator=g, device=X.device, dtype=torch.float32)
+    dt = torch.float64 if prec == nys.FP64 else torch.float32
+    V = torch.randn((X.shape[0], m), generator=g, device=X.device, dtype=dt)
     out = torch.empty_like(V)
     nys.kernel_matvec(X, X, V, nys.RBF, sigma, prec, out=out)     # untimed first call
     torch.cuda.synchronize()
@@ -367,7 +371,12 @@ def main():
     t_kmv1 = time_kernel_matvec(nys, torch, X, w.sigma, 1, prec, args.kmv_reps)
     log(args, f"kernel_matvec m=1: {t_kmv1 * 1e3:.1f} ms")
     if args.kmv_only:
-        print(json.dumps({"kernel_matvec_ms": t_kmv * 1e3, "tflops": kmv_tflops, "m1_ms": t_kmv1 * 1e3}))
+        res = {"kernel_matvec_ms": t_kmv * 1e3, "tflops": kmv_tflops, "m1_ms": t_kmv1 * 1e3}
+        for mc in [int(c) for c in args.kmv_fp64.split(",") if c.strip()]:
+            t64 = time_kernel_matvec(nys, torch, X, w.sigma, mc, nys.FP64, args.kmv_reps)
+            log(args, f"float64 kernel_matvec m={mc}: {t64 * 1e3:.1f} ms")
+            res[f"fp64_m{mc}_ms"] = t64 * 1e3
+        print(json.dumps(res))
         return
 
     ws = torch.empty(nys.nys_workspace_bytes(nys.OP_SOLVE, n, 0, d, r, m, prec), dtype=torch.uint8, device=dev)
