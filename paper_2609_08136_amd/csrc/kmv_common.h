@@ -135,13 +135,16 @@ __device__ inline typename Tr<PREC>::F kernel_value(typename Tr<PREC>::F t,
       return k;
     }
   } else {
+    // The exponent is -kappa |x - y|^2 up to rounding, so a positive t is a rounding
+    // excess near the diagonal: exp2 of it differs from 1 by no more than that
+    // rounding and needs no clamp (fminf would also cost a canonicalising max).  The
+    // Laplacian's square root needs -t >= 0: one v_med3 clamps it.
     if constexpr (KIND == NYS_RBF) {
-      F tt = fminf(t, 0.0f);
-      F k = __builtin_amdgcn_exp2f(tt);
-      if constexpr (DERIV) k *= (-tt) * dcoef;
+      F k = __builtin_amdgcn_exp2f(t);
+      if constexpr (DERIV) k *= (-t) * dcoef;
       return k;
     } else {
-      F dist = __builtin_sqrtf(fmaxf(-t, 0.0f));
+      F dist = __builtin_sqrtf(__builtin_amdgcn_fmed3f(-t, 0.0f, 3.0e38f));
       F k = __builtin_amdgcn_exp2f(-cL * dist);
       if constexpr (DERIV) k *= dist * dcoef;
       return k;
@@ -149,7 +152,7 @@ __device__ inline typename Tr<PREC>::F kernel_value(typename Tr<PREC>::F t,
   }
 }
 
-// ------------------------------------------------------------------ float64 exp, t <= 0
+// ------------------------------------------------------------------ float64 exp, t <= 0 (or a rounding excess above 0)
 // exp(t) = 2^q 2^(j/64) e^r with k = 64 q + j = rint(64 t / ln 2) and
 // r = t - k ln2/64, |r| <= ln2/128.  ln2/64 is split into a 36-bit head (k times it
 // is exact for |k| < 2^17, so the first reduction step is exact) and a tail.
@@ -174,13 +177,14 @@ __device__ inline double exp_neg_tab(double t, const double *tab) {
   const double T = tab[k & 63];
   return ldexp(fma(T, p, T), k >> 6);
 }
-// kernel_value<NYS_FP64, ...> with the table exp
+// kernel_value<NYS_FP64, ...> with the table exp.  RBF: a positive t is a rounding
+// excess (the exponent is -kappa |x - y|^2), which exp_neg_tab evaluates as accurately
+// as a negative one, so it is not clamped.
 template <int KIND, int DERIV>
 __device__ inline double kernel_value_tab(double t, double cL, double dcoef, const double *tab) {
   if constexpr (KIND == NYS_RBF) {
-    const double tt = t < 0.0 ? t : 0.0;
-    double k = exp_neg_tab(tt, tab);
-    if constexpr (DERIV) k *= (-tt) * dcoef;
+    double k = exp_neg_tab(t, tab);
+    if constexpr (DERIV) k *= (-t) * dcoef;
     return k;
   } else {
     const double dist = sqrt(t < 0.0 ? -t : 0.0);
