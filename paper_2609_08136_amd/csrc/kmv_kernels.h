@@ -388,8 +388,15 @@ constexpr int KMV2_THREADS = 512;
 template <bool F16V> struct ProdType { using V = bf8; using S = __bf16; };
 template <> struct ProdType<true> { using V = h8; using S = _Float16; };
 
+// The 16- and (RBF) 32-column tiles run four waves per SIMD (two workgroups per CU)
+// within 128 registers; the 32-column one spills a few registers there and is still
+// faster (517 against 570 ms at n = 1e6, 32 columns).
+template <int KIND, int KSMAX, int TM>
+constexpr int flash2_waves_per_simd() {
+  return KSMAX <= 6 && (TM == 16 || (TM == 32 && KIND == NYS_RBF)) ? 4 : 2;
+}
 template <int KIND, int KSMAX, int TM, bool F16V = false>
-__global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
+__global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, TM>())) void kmv_flash2_kernel(KArgs a) {
   using T = Tr<NYS_BF16X3>;
   using Op = typename T::Op;
   using PV = typename ProdType<F16V>::V;   // operand vector of the K V product
@@ -443,6 +450,10 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
     for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = f4{0, 0, 0, 0};
 
   const float cL = (float)a.cL, dcoef = (float)a.dcoef;
+  // -1 kept opaque to the optimiser, so that kv - h stays an fma with a half operand
+  // (chunks up to 64 columns; the wider tiles measured faster with the plain form)
+  float mone = -1.0f;
+  if constexpr (F16V && TM <= 64) asm volatile("" : "+v"(mone));
   const int64_t njt = (a.nc + TJ - 1) / TJ;
   const int64_t jt0 = (int64_t)split * a.jsteps;
   const int64_t jt1 = jt0 + a.jsteps < njt ? jt0 + a.jsteps : njt;
@@ -557,7 +568,10 @@ __global__ __launch_bounds__(KMV2_THREADS) void kmv_flash2_kernel(KArgs a) {
         const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);
         const PS h = (PS)kv;
         phi[r][e] = h;
-        plo[r][e] = (PS)(kv - (float)h);
+        // kv - h is exact in float32.  For the fp16 split, as one fma with a half
+        // operand it becomes a single v_fma_mix{lo,hi}_f16
+        if constexpr (F16V && TM <= 64) plo[r][e] = (PS)__builtin_fmaf((float)h, mone, kv);
+        else plo[r][e] = (PS)(kv - (float)h);
       }
     }
     // V operands are read one column block ahead of the MFMAs that use them
