@@ -104,7 +104,7 @@ def run_other(args):
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     wl = args.workload
     out = {"n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "data": "synthetic", "unit": "s", "device": torch.cuda.get_device_name(0)}
+           "vs_baseline": None, "data": "synthetic", "unit": "s", "device": device_label(torch)}
 
     if wl == "plain_fp64":
         w = ni.plain_fp64(args.seed)
@@ -229,6 +229,14 @@ def cpu_model() -> str:
 
 # Kernel sources whose hash a committed HBM-counter summary must match to be reported.
 KERNEL_SOURCES = ["kmv_common.h", "kmv_kernels.h", "kmv_host.hip", "kmv_bf16.hip", "kmv_f16.hip"]
+
+
+def device_label(torch) -> str:
+    """Marketing name of GPU 0, else its gfx architecture (the name can be empty)."""
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "") or ""
+    name = props.name or ""
+    return f"{name} ({arch})" if name and arch else (name or arch)
 
 
 def kernel_source_hash() -> str:
@@ -473,7 +481,7 @@ def main():
                   "sampled_rows_max_relres": sampled, "max_iters_per_lambda": per_lambda,
                   "sum_column_iters": sum(iters), "sum_refinements": sum(refs), "rank": P.rank, "nu": P.nu},
         "cpu_baseline": cpu,
-        "device": torch.cuda.get_device_name(0),
+        "device": device_label(torch),
     }
     print(json.dumps(out))
 
