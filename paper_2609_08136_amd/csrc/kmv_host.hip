@@ -335,7 +335,7 @@ std::vector<Tuned> g_tuned;
 
 bool kmv_tile_valid(int prec, int tm) {
   switch (prec) {
-    case NYS_FP64: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
+    case NYS_FP64: return tm == 16 || tm == 32 || tm == 48 || tm == 64 || tm == 96 || tm == 128 || tm == 256;
     case NYS_FP32: return tm == 32 || tm == 64 || tm == 128;
     case NYS_F16X3_D10: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
     default: return tm == 32 || tm == 64 || tm == 128 || tm == 256;
@@ -404,17 +404,28 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : 128);
       p.r = 2;
     } else {
-      p.tm = m <= 16 ? 16 : (m <= 32 ? 32 : (m <= 64 ? 64 : (m <= 128 ? 128 : 256)));
+      // float64: the chunk width with the least chunks x cost, the cost of one chunk
+      // measured at n = 1e6, d = 16 (seconds; the exponent is recomputed per chunk)
+      static const int tms[] = {16, 32, 48, 64, 96, 128, 256};
+      static const double cost[] = {1.57, 2.00, 2.50, 2.98, 3.94, 4.63, 8.55};
+      double best = 1e300;
+      for (int t = 0; t < 7; ++t) {
+        const double c = (double)ceil_div(m, tms[t]) * cost[t];
+        if (c < best) {
+          best = c;
+          p.tm = tms[t];
+        }
+      }
       p.r = 2;
     }
     const int tuned = kmv_tune_get(f16v ? NYS_F16X3_D10 : prec0, m);
     if (tuned > 0) p.tm = tuned;
-    // float64: 64- and 256-column chunks take one 16-row block per wave (four waves
-    // per SIMD at 64 columns; 256 columns within the register budget).  Measured at
-    // n = 1e6: 64 columns 2.98 s against 3.23 s with two blocks, 256 columns 8.6 s
-    // against 9.4 s for two 128-column chunks; 128 columns are faster with two
-    // blocks (4.83 s against 5.06 s).
-    if (prec == NYS_FP64) p.r = p.tm == 64 || p.tm == 256 ? 1 : 2;
+    // float64: 48-, 64- and 256-column chunks take one 16-row block per wave (four
+    // waves per SIMD up to 64 columns; 256 columns within the register budget).
+    // Measured at n = 1e6: 64 columns 2.98 s against 3.23 s with two blocks, 256
+    // columns 8.6 s against 9.4 s for two 128-column chunks; 128 columns are faster
+    // with two blocks (4.83 s against 5.06 s).
+    if (prec == NYS_FP64) p.r = p.tm == 48 || p.tm == 64 || p.tm == 256 ? 1 : 2;
     if (ov.set && ov.path == 1) {
       if (ov.tm) p.tm = ov.tm;
       if (ov.r) p.r = ov.r;

@@ -637,7 +637,7 @@ __global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, T
 // workgroups per CU).
 template <int KIND, int KSMAX, int TM, int R>
 constexpr int flash64_waves_per_simd() {
-  if constexpr (R == 1) return KSMAX <= 8 && TM == 64 ? 4 : 2;
+  if constexpr (R == 1) return KSMAX <= 8 && TM <= 64 ? 4 : 2;
   return (TM == 16 && KSMAX <= 8) || (TM == 32 && KSMAX <= 5 && KIND == NYS_RBF) ? 4 : 2;
 }
 template <int KIND, int KSMAX, int TM, int R>

@@ -240,7 +240,7 @@ def test_fp16_product_is_more_accurate(nys):
     assert e_h < e_bf / 8 and e_h < 2.0 ** -19
 
 
-@pytest.mark.parametrize("prec,widths", [(0, (16, 32, 64, 128, 256)), (1, (32, 64, 128)), (2, (32, 64, 128, 256)),
+@pytest.mark.parametrize("prec,widths", [(0, (16, 32, 48, 64, 96, 128, 256)), (1, (32, 64, 128)), (2, (32, 64, 128, 256)),
                                          (5, (16, 32, 64, 128, 256))])
 def test_every_chunk_width_matches_oracle(nys, prec, widths):
     """Every column-chunk width the autotuner may choose gives the same products (to
