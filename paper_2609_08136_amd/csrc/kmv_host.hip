@@ -404,13 +404,18 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.tm = m <= 32 ? 32 : (m <= 64 ? 64 : 128);
       p.r = 2;
     } else {
-      // float64: the chunk width with the least chunks x cost, the cost of one chunk
-      // measured at n = 1e6, d = 16 (seconds; the exponent is recomputed per chunk)
+      // float64: the chunk width with the least cost over its full chunks plus the
+      // narrowest chunk that holds the remainder, the cost of one chunk measured at
+      // n = 1e6, d = 16 (seconds; every chunk recomputes the exponents)
       static const int tms[] = {16, 32, 48, 64, 96, 128, 256};
       static const double cost[] = {1.57, 2.00, 2.50, 2.98, 3.94, 4.63, 8.55};
       double best = 1e300;
       for (int t = 0; t < 7; ++t) {
-        const double c = (double)ceil_div(m, tms[t]) * cost[t];
+        const int64_t full = ceil_div(m, tms[t]) - 1;
+        const int64_t rem = m - full * tms[t];
+        int u = 0;
+        while (tms[u] < rem) ++u;
+        const double c = (double)full * cost[t] + cost[u];
         if (c < best) {
           best = c;
           p.tm = tms[t];
@@ -456,7 +461,38 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   p.jsteps = (int)ceil_div(njt, splits);
   p.splits = (int)ceil_div(njt, p.jsteps);
   p.m_pad = p.path == 1 ? (int64_t)chunks * p.tm : 0;
+  // the last chunk takes the narrowest width that holds the remaining columns (a
+  // second launch; every chunk recomputes the exponents, so a narrower one is cheaper)
+  if (p.path == 1 && chunks > 1 && !(ov.set && ov.path == 1)) {
+    const int rem = m - (chunks - 1) * p.tm;
+    const int key = f16v ? NYS_F16X3_D10 : prec0;
+    for (int t : {16, 32, 48, 64, 96, 128, 256}) {
+      if (t >= p.tm) break;
+      if (t >= rem && kmv_tile_valid(key, t)) {
+        p.tail_tm = t;
+        break;
+      }
+    }
+  }
   return p;
+}
+
+// The plan of the last chunk of a plan with a narrower tail: same precision path and
+// column splits, one chunk of tail_tm columns.
+static KmvPlan tail_plan(const KmvPlan &p, int prec) {
+  KmvPlan t = p;
+  t.tm = p.tail_tm;
+  t.tail_tm = 0;
+  t.m_pad = t.tm;
+  prec = kernel_prec(prec);
+  if (prec == NYS_FP64) {
+    t.r = t.tm == 48 || t.tm == 64 || t.tm == 256 ? 1 : 2;
+    t.waves = 8;
+  } else if (prec == NYS_BF16X3 && !p.f16v) {
+    t.r = 2;
+    t.waves = t.tm >= 64 ? 8 : 4;
+  }
+  return t;
 }
 
 void kmv_scratch_sizes(const KmvPlan &p, int64_t nr, int64_t nc, int m, int prec,
@@ -499,6 +535,19 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec, c
                 int ldo, double alpha, double beta, void *partial, void *vhi, void *vlo,
                 hipStream_t s) {
   if (m <= 0 || rows.n <= 0) return NYS_OK;
+  if (plan.path == 1 && plan.tail_tm > 0 && !deriv) {
+    // full chunks, then the narrower last chunk as a launch of its own
+    const int m1 = (int)(ceil_div(m, plan.tm) - 1) * plan.tm;
+    KmvPlan head = plan;
+    head.tail_tm = 0;
+    head.m_pad = m1;
+    NYS_RETURN_IF(kmv_run(head, k, deriv, prec, rows, cols, same_points, V, m1, ldv, Out, ldo, alpha, beta,
+                          partial, vhi, vlo, s));
+    const size_t eb = kernel_prec(prec) == NYS_FP64 ? 8 : 4;
+    return kmv_run(tail_plan(plan, prec), k, deriv, prec, rows, cols, same_points,
+                   reinterpret_cast<const char *>(V) + (size_t)m1 * eb, m - m1, ldv,
+                   reinterpret_cast<char *>(Out) + (size_t)m1 * eb, ldo, alpha, beta, partial, vhi, vlo, s);
+  }
   prec = kernel_prec(prec);
   const int ksmax = ksmax_for(prec, rows.Kp);
   if (ksmax < 0) {

@@ -120,6 +120,7 @@ struct KmvPlan {
   int jsteps = 0;        // j tiles per split
   int64_t m_pad = 0;     // flash BF16: padded width of the split V
   int f16v = 0;          // flash: fp16 K V product with column-scaled V
+  int tail_tm = 0;       // flash: width of the last chunk when narrower than tm (its own launch)
 };
 
 // Decide the launch shape for an (nr, nc, m, prec) product.
