@@ -64,11 +64,13 @@ class NysError(RuntimeError):
 
 
 _lib = None
+_lib_file = None
+_lib_id = None
 
 
 def load(path: str | None = None):
     """Load libnys.so (built by paper_2609_08136_amd.build); raises if it is absent."""
-    global _lib
+    global _lib, _lib_file
     if _lib is not None:
         return _lib
     p = path or LIB_PATH
@@ -98,7 +100,30 @@ def load(path: str | None = None):
                  "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile"):
         getattr(lib, name).restype = c_i32
     _lib = lib
+    _lib_file = p
     return lib
+
+
+def library_id() -> str:
+    """First 16 hex digits of the SHA-256 of the loaded libnys.so: tuned chunk widths
+    belong to one build."""
+    global _lib_id
+    if _lib_id is None:
+        import hashlib
+        load()
+        h = hashlib.sha256()
+        with open(_lib_file, "rb") as f:
+            for block in iter(lambda: f.read(1 << 20), b""):
+                h.update(block)
+        _lib_id = h.hexdigest()[:16]
+    return _lib_id
+
+
+def device_tag(device) -> str:
+    """Name of a GPU for cache keys: its marketing name and gfx architecture (the name
+    alone can be empty)."""
+    props = torch.cuda.get_device_properties(device)
+    return f"{props.name}|{getattr(props, 'gcnArchName', '')}"
 
 
 def version() -> str:
@@ -357,11 +382,13 @@ def autotune(X, kind: int, sigma: float, prec: int, m_max: int, cache: str | Non
     """Tune every column-count bucket up to m_max (see TUNE_BUCKETS), timing rows
     X[0:n_rows] against all of X (the chunk width is a property of the tile, so a
     row subsample keeps the tuning short).  With `cache`
-    (a JSON file), choices recorded for the same device, precision, kernel and point
-    set shape are installed instead of re-timed, and new ones are added to it."""
+    (a JSON file), choices recorded for the same device, library build, precision,
+    kernel and point set shape are installed instead of re-timed, and new ones are
+    added to it."""
     import json
     n_rows = X.shape[0] if n_rows is None else min(int(n_rows), X.shape[0])
-    key = f"{torch.cuda.get_device_name(X.device)}|prec{prec}|kind{kind}|n{X.shape[0]}|d{X.shape[1]}|rows{n_rows}"
+    key = (f"{device_tag(X.device)}|lib{library_id()}|prec{prec}|kind{kind}|n{X.shape[0]}|d{X.shape[1]}"
+           f"|rows{n_rows}")
     table = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:

@@ -153,3 +153,11 @@ def test_autotune_argument_errors(lib):
     b = ctypes.c_size_t(0)
     assert lib.nys_workspace_bytes(6, 1000, 4000, 16, 0, 64, nys.F16X3_D10, ctypes.byref(b)) == nys.OK
     assert b.value >= (4000 + 1000) * 64 * 4
+
+
+def test_library_id_is_the_content_hash_of_the_loaded_build(lib):
+    import hashlib
+    with open(nys.LIB_PATH, "rb") as f:
+        want = hashlib.sha256(f.read()).hexdigest()[:16]
+    assert nys.library_id() == want
+    assert re.fullmatch(r"[0-9a-f]{16}", nys.library_id())
