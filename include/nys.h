@@ -296,7 +296,12 @@ int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, dou
  * choice is process-wide; query workspace sizes after tuning.  X is n x d
  * float64 (device), ws at least nys_workspace_bytes(NYS_OP_AUTOTUNE, n_rows, n,
  * d, 0, m, prec).  nys_set_tile installs a width (e.g. from a cache of earlier
- * runs; tm = 0 removes the range) and nys_clear_tiles drops every choice. */
+ * runs; tm = 0 removes the range) and nys_clear_tiles drops every choice.
+ * Valid widths: FP64 16, 32, 48, 64, 96, 128, 256 (without a tuned width its
+ * planner takes the least measured cost); FP32 32, 64, 128; F16X3_D10 16..256 and
+ * the other bf16 splits 32..256 in powers of two.  Whatever the width, the last
+ * chunk of a product runs at the narrowest width that holds the remaining
+ * columns. */
 typedef struct {
   int32_t tm;        /* column-chunk width */
   int32_t reserved;
