@@ -122,6 +122,24 @@ def test_fp64_kernel_entries_over_the_whole_exponent_range(nys, kind, m):
     assert ref.min() == 0.0 and np.all(got[ref == 0.0] <= 1e-300) and got.min() >= 0.0
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2, 5])
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+@pytest.mark.parametrize("m", [1, 40])
+def test_matvec_duplicate_points(nys, prec, kind, m):
+    """Every point three times: off-diagonal pairs at distance zero, whose computed
+    exponent is a rounding residue of either sign (the RBF epilogue does not clamp it)."""
+    rng = np.random.default_rng(17 + m)
+    X = np.repeat(rng.standard_normal((200, 16)) * 3.0, 3, axis=0)
+    V = rng.standard_normal((600, m))
+    if prec != 0:
+        V = V.astype(np.float32).astype(np.float64)
+    sigma = 4.0
+    print(f"case duplicates prec={prec} kind={kind} m={m}", flush=True)
+    got = run(nys, X, X, V, kind, sigma, prec)
+    ref = o.kernel_matvec(X, X, V, kind, sigma)
+    assert np.max(np.abs(got - ref) / bound(X, X, V, kind, sigma, prec)) <= 1.0
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_matvec_rectangular(nys, prec):
     check(nys, 333, 1201, 16, 1, o.RBF, prec, same=False, seed=3)
