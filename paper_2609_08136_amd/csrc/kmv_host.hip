@@ -307,22 +307,6 @@ __global__ void split_reduce_kernel(const F *partial, int splits, int64_t nr, in
 }
 
 // ------------------------------------------------------------------ planning
-namespace {
-std::mutex g_ovr_mu;
-struct Override {
-  int set = 0, path = 0, tm = 0, r = 0, splits = 0;
-} g_ovr[3];
-}  // namespace
-
-void kmv_set_override(int prec, int path, int tm, int r, int splits) {
-  std::lock_guard<std::mutex> lk(g_ovr_mu);
-  g_ovr[prec] = Override{1, path, tm, r, splits};
-}
-void kmv_clear_override() {
-  std::lock_guard<std::mutex> lk(g_ovr_mu);
-  for (auto &o : g_ovr) o = Override{};
-}
-
 // Tile widths chosen by the autotuner (nys_autotune / nys_set_tile), per original
 // precision and column-count range.  kmv_plan takes the chunk width from here.
 namespace {
@@ -385,12 +369,7 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   // float64: the pipelined tile beats the row-sum tile from 5 columns on (16-column
   // chunks); the fp16-product tile (16-column chunk) beats it at every width
   const int mm_cap = prec == NYS_FP64 ? 4 : (f16v ? 0 : 16);
-  Override ov;
-  {
-    std::lock_guard<std::mutex> lk(g_ovr_mu);
-    ov = g_ovr[prec];
-  }
-  if (m <= mm_cap && !(ov.set && ov.path == 1)) {
+  if (m <= mm_cap) {
     p.path = 0;
     p.mm = 1;
     while (p.mm < m) p.mm *= 2;
@@ -431,10 +410,6 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
     // columns 8.6 s against 9.4 s for two 128-column chunks; 128 columns are faster
     // with two blocks (4.83 s against 5.06 s).
     if (prec == NYS_FP64) p.r = p.tm == 48 || p.tm == 64 || p.tm == 256 ? 1 : 2;
-    if (ov.set && ov.path == 1) {
-      if (ov.tm) p.tm = ov.tm;
-      if (ov.r) p.r = ov.r;
-    }
     // BF16X3 chunks of >= 64 columns run on the pipelined eight-wave tile; the fp16
     // product exists only there (every chunk width)
     if (prec == NYS_BF16X3 && p.tm >= 64 && p.r == 2) p.waves = 8;
@@ -457,13 +432,12 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   // enough workgroups to fill 256 CUs several times over; each split keeps >= 8 tiles
   int64_t want = ceil_div(2048, ntiles * chunks);
   int64_t splits = std::max<int64_t>(1, std::min<int64_t>(want, njt / 8));
-  if (ov.set && ov.splits > 0) splits = std::min<int64_t>(ov.splits, std::max<int64_t>(njt, 1));
   p.jsteps = (int)ceil_div(njt, splits);
   p.splits = (int)ceil_div(njt, p.jsteps);
   p.m_pad = p.path == 1 ? (int64_t)chunks * p.tm : 0;
   // the last chunk takes the narrowest width that holds the remaining columns (a
   // second launch; every chunk recomputes the exponents, so a narrower one is cheaper)
-  if (p.path == 1 && chunks > 1 && !(ov.set && ov.path == 1)) {
+  if (p.path == 1 && chunks > 1) {
     const int rem = m - (chunks - 1) * p.tm;
     const int key = f16v ? NYS_F16X3_D10 : prec0;
     for (int t : {16, 32, 48, 64, 96, 128, 256}) {

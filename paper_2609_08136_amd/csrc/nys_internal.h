@@ -140,9 +140,6 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec,
                 int m, int ldv, void *Out, int ldo, double alpha, double beta, void *partial,
                 void *vhi, void *vlo, hipStream_t s);
 
-// Test hook: force a plan shape for a kernel precision (0 = use the heuristic).
-void kmv_set_override(int prec, int path, int tm, int r, int splits);
-void kmv_clear_override();
 // Autotuned chunk widths: tm for columns m in [m_lo, m_hi] of a precision (tm 0 removes).
 bool kmv_tile_valid(int prec, int tm);
 void kmv_tune_set(int prec, int m_lo, int m_hi, int tm);
