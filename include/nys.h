@@ -314,6 +314,14 @@ int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int
 int32_t nys_set_tile(int32_t prec, int32_t m_lo, int32_t m_hi, int32_t tm);
 void nys_clear_tiles(void);
 
+/* Host-only query of the plan kernel_matvec would use for an n x n product with m
+ * columns at precision prec and dimension d (tuned widths included): *tm gets the
+ * column-chunk width and *tail_tm the width of the last chunk when it is narrower
+ * (0 otherwise); both are 0 when m runs on the row-sum tile.  No device work, no
+ * allocation.  Returns NYS_EINVAL for an unsupported precision, n < 1, m < 1, d out
+ * of range or a null output. */
+int32_t nys_plan_chunks(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *tm, int32_t *tail_tm);
+
 const char *nys_last_error(void);
 
 /* Library version string. */

@@ -28,7 +28,7 @@ OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BA
 
 EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "nys_sketch", "nys_precond_build",
            "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_autotune", "nys_set_tile",
-           "nys_clear_tiles", "nys_last_error", "nys_version")
+           "nys_clear_tiles", "nys_plan_chunks", "nys_last_error", "nys_version")
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -96,8 +96,9 @@ def load(path: str | None = None):
     lib.nys_set_tile.argtypes = [c_i32, c_i32, c_i32, c_i32]
     lib.nys_clear_tiles.argtypes = []
     lib.nys_clear_tiles.restype = None
+    lib.nys_plan_chunks.argtypes = [c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
     for name in ("kernel_matvec", "nys_sketch", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
-                 "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile"):
+                 "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile", "nys_plan_chunks"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     _lib_file = p
@@ -375,6 +376,14 @@ def nys_set_tile(prec: int, m_lo: int, m_hi: int, tm: int) -> None:
 
 def nys_clear_tiles() -> None:
     load().nys_clear_tiles()
+
+
+def nys_plan_chunks(prec: int, n: int, d: int, m: int) -> tuple[int, int]:
+    """(chunk width, narrower last-chunk width or 0) the product would use for an
+    n x n product with m columns; (0, 0) on the row-sum tile.  Host only."""
+    tm, tail = c_i32(0), c_i32(0)
+    _check(load().nys_plan_chunks(prec, n, d, m, ctypes.byref(tm), ctypes.byref(tail)))
+    return tm.value, tail.value
 
 
 def autotune(X, kind: int, sigma: float, prec: int, m_max: int, cache: str | None = None, reps: int = 1,

@@ -408,6 +408,17 @@ int32_t nys_set_tile(int32_t prec, int32_t m_lo, int32_t m_hi, int32_t tm) {
 
 void nys_clear_tiles(void) { kmv_tune_clear(); }
 
+int32_t nys_plan_chunks(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *tm, int32_t *tail_tm) {
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (n < 1 || m < 1) return einval("need n >= 1 and m >= 1");
+  if (d < 1 || d > max_dim(prec)) return einval("d out of range for this precision");
+  if (!tm || !tail_tm) return einval("null pointer");
+  const KmvPlan p = kmv_plan(n, n, m, prec, packed_kp(d, prec));
+  *tm = p.path == 1 ? p.tm : 0;
+  *tail_tm = p.path == 1 ? p.tail_tm : 0;
+  return NYS_OK;
+}
+
 int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int64_t n_rows, int32_t d,
                      int32_t m, int32_t m_lo, int32_t reps, nys_tile_choice *best, void *ws, size_t ws_bytes,
                      void *stream) {

@@ -161,3 +161,53 @@ def test_library_id_is_the_content_hash_of_the_loaded_build(lib):
         want = hashlib.sha256(f.read()).hexdigest()[:16]
     assert nys.library_id() == want
     assert re.fullmatch(r"[0-9a-f]{16}", nys.library_id())
+
+
+def test_plan_chunks_last_chunk_and_float64_costs(lib):
+    """The chunk plan (host logic only): the last chunk runs at the narrowest width that
+    holds the remaining columns, and the float64 planner minimises the measured chunk
+    cost (widths 16..256 including 48 and 96)."""
+    nys.nys_clear_tiles()
+    n, d = 1_000_000, 16
+    # fp16 product: 256-column chunks, the remainder in the narrowest chunk that holds it
+    assert nys.nys_plan_chunks(nys.F16X3_D10, n, d, 512) == (256, 0)
+    assert nys.nys_plan_chunks(nys.F16X3_D10, n, d, 320) == (256, 64)
+    assert nys.nys_plan_chunks(nys.F16X3_D10, n, d, 270) == (256, 16)
+    assert nys.nys_plan_chunks(nys.F16X3_D10, n, d, 1) == (16, 0)      # fp16 tile at every width
+    # float32: 128-column chunks, tail from its widths (32, 64, 128)
+    assert nys.nys_plan_chunks(nys.FP32, n, d, 300) == (128, 64)
+    assert nys.nys_plan_chunks(nys.FP32, n, d, 260) == (128, 32)
+    # bf16 splits: no 16-column tile
+    assert nys.nys_plan_chunks(nys.BF16X3, n, d, 270) == (256, 32)
+    # float64: row-sum tile up to 4 columns, then the cheapest chunking
+    assert nys.nys_plan_chunks(nys.FP64, n, d, 4) == (0, 0)
+    assert nys.nys_plan_chunks(nys.FP64, n, d, 40) == (48, 0)
+    assert nys.nys_plan_chunks(nys.FP64, n, d, 80) == (96, 0)
+    assert nys.nys_plan_chunks(nys.FP64, n, d, 144) == (128, 16)
+    assert nys.nys_plan_chunks(nys.FP64, n, d, 200) == (256, 0)
+    assert nys.nys_plan_chunks(nys.FP64, n, d, 384) == (256, 128)
+    assert nys.nys_plan_chunks(nys.FP64, n, d, 512) == (256, 0)
+    # every plan's widths are tiles of that precision, and the chunks cover m
+    for prec in (nys.FP64, nys.FP32, nys.BF16X3, nys.F16X3_D10):
+        for m in range(1, 600, 7):
+            tm, tail = nys.nys_plan_chunks(prec, n, d, m)
+            if tm == 0:
+                assert prec == nys.FP64 and m <= 4 or prec != nys.FP64 and m <= 16
+                continue
+            full = -(-m // tm) - 1
+            assert tail == 0 or (tail < tm and m - full * tm <= tail)
+            assert full * tm + (tail or tm) >= m
+
+
+def test_plan_chunks_follow_tuned_widths_and_reject_bad_arguments(lib):
+    try:
+        nys.nys_set_tile(nys.F16X3_D10, 257, 512, 128)
+        assert nys.nys_plan_chunks(nys.F16X3_D10, 10**6, 16, 300) == (128, 64)
+    finally:
+        nys.nys_clear_tiles()
+    tm, tail = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.nys_plan_chunks(9, 1000, 16, 10, ctypes.byref(tm), ctypes.byref(tail)) == nys.EINVAL
+    assert lib.nys_plan_chunks(nys.FP64, 0, 16, 10, ctypes.byref(tm), ctypes.byref(tail)) == nys.EINVAL
+    assert lib.nys_plan_chunks(nys.FP64, 1000, 16, 0, ctypes.byref(tm), ctypes.byref(tail)) == nys.EINVAL
+    assert lib.nys_plan_chunks(nys.F16X3_D10, 1000, 25, 10, ctypes.byref(tm), ctypes.byref(tail)) == nys.EINVAL
+    assert lib.nys_plan_chunks(nys.FP64, 1000, 16, 10, None, ctypes.byref(tail)) == nys.EINVAL
