@@ -4,14 +4,21 @@
 Workload (default): the batched lambda-grid problem at n = 1e6 points, d = 16,
 RBF kernel sigma = 4, 64 right-hand sides b_c = sign(X w_c) times 8 lambdas
 log-spaced over [1e-7 n, 1e-3 n] (512 independent columns), one shared Nystrom
-sketch of rank 500, BF16X3 kernel products, float32 CG with float64 residual
+sketch of rank 500, F16X3_D10 kernel products, float32 CG with float64 residual
 refinement, tolerance 1e-6 on the float64 true relative residual.
 
 One step = sketch + preconditioner build + PCG to tolerance for every column
 (the paper counts the preconditioner build in the solve time, section "Large-Scale
 Ridge Regression with NysPCG").  Data generation, device placement and the
-Gaussian test matrix are outside the timer; one warmup capped at 10 iterations
-precedes the timed steps (section "Hardware, Timing, and Solver Settings").
+Gaussian test matrix are outside the timer; one warm-up capped at 10 iterations
+precedes the timed steps and the clock stops after a device synchronisation
+(section "Hardware, Timing, and Solver Settings").
+
+One step at n = 1e6 takes minutes, so --steps and --warmup are upper bounds under a
+wall-clock budget (--budget-s, counted from process start): at most one warm-up, the
+first timed step always, and a further one only when its projected end (the slowest
+step so far, plus the time the report needs) fits the budget.  The JSON line reports
+the counts actually run.  Progress goes to stderr, one line per phase.
 
 Prints one JSON line.
 """
@@ -26,22 +33,36 @@ import statistics
 import sys
 import time
 
+T_START = time.monotonic()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "NysPCG time-to-1e-6 rel. residual + kernel_matvec TFLOP/s, n=1e6 d=16"
-PEAK_BF16_TFLOPS = 2500.0      # MI355X dense bf16 MFMA
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense bf16 / fp16 MFMA (published)
+PEAK_F64_TFLOPS = 78.6         # MI355X float64 MFMA (published)
 HBM_GBS = 8000.0
+
+
+def phase(msg: str) -> None:
+    print(f"[bench {time.monotonic() - T_START:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def elapsed() -> float:
+    return time.monotonic() - T_START
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1, help="timed steps (upper bound under --budget-s)")
+    ap.add_argument("--warmup", type=int, default=1, help="warm-up steps (at most one is run)")
+    ap.add_argument("--budget-s", type=float, default=540.0,
+                    help="wall-clock budget from process start; no timed step starts that would end past it")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", default="",
+                    help="comma-separated data seeds, one timed step each in turn (default: --seed)")
     ap.add_argument("--refine-every", type=int, default=0)
     ap.add_argument("--refine-mode", type=int, default=1)
     ap.add_argument("--refine-reduction", type=float, default=1e-3,
@@ -49,6 +70,8 @@ def parse():
     ap.add_argument("--kmv-reps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-m1", action="store_true", help="skip the single right-hand-side solve")
+    ap.add_argument("--no-probe", action="store_true", help="skip the ceiling probes")
     ap.add_argument("--kmv-only", action="store_true", help="time the kernel product only (profiling)")
     ap.add_argument("--kmv-fp64", default="",
                     help="with --kmv-only: also time the float64 product (the refinement residual) at these "
@@ -57,7 +80,7 @@ def parse():
                     help="with --kmv-only: first run one plain 1 GiB device copy, whose HBM counter readings "
                          "scale the kernel's (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--prec", default="f16x3_d10", choices=["bf16x3", "bf16x3_d6", "bf16x3_d10", "f16x3_d10"],
+    ap.add_argument("--prec", default="f16x3_d10", choices=["bf16x3", "bf16x3_d6", "bf16x3_d10", "f16x3_d10", "fp32"],
                     help="kernel-product precision of the batched workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the tile autotuner (heuristic chunk widths)")
@@ -65,7 +88,7 @@ def parse():
                     help="JSON cache of autotuned chunk widths")
     ap.add_argument("--workload", default="batched_lambda_grid",
                     choices=["batched_lambda_grid", "plain_fp64", "matrix_free_fp32", "precision_variant",
-                             "differentiation"],
+                             "differentiation", "grid_vs_fp32", "cg_ratio"],
                     help="batched_lambda_grid is the headline workload; the others are recorded separately")
     return ap.parse_args()
 
@@ -82,9 +105,8 @@ def _timed(torch, fn):
 
 def _solve_once(nys, torch, X, B, w, Om0, prec, sketch_prec, **opts):
     """sketch + build + solve; returns (Xsol, info, rc, P, seconds)."""
-    Om = Om0.clone()
     def run():
-        P = nys.build_preconditioner(X, Om, w.kind, w.sigma, sketch_prec)
+        P = nys.build_preconditioner(X, Om0, w.kind, w.sigma, sketch_prec)
         x, info, rc = nys.nyspcg_solve(X, B, w.lambdas, w.kind, w.sigma, P, tol=w.tol, prec=prec, **opts)
         return x, info, rc, P
     (x, info, rc, P), t = _timed(torch, run)
@@ -96,7 +118,6 @@ def run_other(args):
     import torch
 
     import nys_inputs as ni
-    import oracle as o
     import paper_2609_08136_amd as nys
 
     nys.load()
@@ -111,20 +132,14 @@ def run_other(args):
         X, B, Om0 = T(w.X), T(w.B), T(ni.gaussian_test_matrix(w.n, w.r, args.seed))
         _solve_once(nys, torch, X, B, w, Om0, nys.FP64, nys.FP64, max_iters=10)          # warmup
         x, info, rc, P, t = _solve_once(nys, torch, X, B, w, Om0, nys.FP64, nys.FP64, check_true=True)
-        K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
-        ref = o.direct_solve(K, w.B[:, 0], w.lambdas[0])
-        xs = x.cpu().numpy().reshape(-1)
-        t0 = time.perf_counter()
-        o.nyspcg_dense(w.X, w.B, w.lambdas, w.kind, w.sigma, ni.gaussian_test_matrix(w.n, w.r, args.seed), tol=w.tol)
-        t_cpu = time.perf_counter() - t0
+        cpu = cpu_baseline_plain(w, x.cpu().numpy().reshape(-1), ni.gaussian_test_matrix(w.n, w.r, args.seed))
         out.update(metric="NysPCG time-to-1e-8 rel. residual, n=2000 d=10, FP64", value=round(t, 5),
                    ms_per_step=round(t * 1e3, 3), dtype="f64",
                    config={"workload": "plain_fp64", "n": w.n, "d": w.d, "rank": w.r, "lambda": w.lambdas[0],
                            "sigma": w.sigma, "tol": w.tol},
                    solve={"status": rc, "iters": info[0]["iters"], "relres_true": info[0]["relres_true"],
-                          "rel_error_vs_cholesky": float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))},
-                   cpu_baseline={"value": t_cpu, "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
-                                 "sample": "the whole workload: dense K, Nystrom, textbook PCG (float64 NumPy)"})
+                          "rel_error_vs_cholesky": cpu.pop("rel_error_vs_cholesky")},
+                   cpu_baseline=cpu)
     elif wl == "matrix_free_fp32":
         w = ni.matrix_free_fp32(args.seed)
         X, B = T(w.X), T(w.B)
@@ -169,6 +184,8 @@ def run_other(args):
                    config={"workload": "precision_variant", "n": w.n, "d": w.d, "rank": w.r,
                            "lambda": w.lambdas[0], "sigma": w.sigma, "tol": w.tol, "refine_every": 20},
                    runs=res, speedup_vs_fp32=round(res["fp32"]["seconds"] / res["bf16x3"]["seconds"], 3))
+    elif wl in ("grid_vs_fp32", "cg_ratio"):
+        out.update(grid_or_cg(args, nys, torch, ni, dev, T))
     else:  # differentiation
         from paper_2609_08136_amd import autograd as ag
         w = ni.differentiation(args.seed)
@@ -179,7 +196,7 @@ def run_other(args):
         opts = dict(tol=1e-10, prec=nys.FP64)
 
         def loss_grad(theta):
-            P = nys.build_preconditioner(X, Om0.clone(), w.kind, math.exp(theta[1]), nys.FP64)
+            P = nys.build_preconditioner(X, Om0, w.kind, math.exp(theta[1]), nys.FP64)
             tl = torch.tensor(theta[0], dtype=torch.float64, device=dev, requires_grad=True)
             ts = torch.tensor(theta[1], dtype=torch.float64, device=dev, requires_grad=True)
             L = ag.validation_loss(X, y, Xv, yv, tl, ts, w.kind, P, opts)
@@ -209,6 +226,80 @@ def run_other(args):
                                      "loss": [round(v, 8) for v in hist],
                                      "lambda": math.exp(theta[0]), "sigma": math.exp(theta[1])})
     print(json.dumps(out))
+
+
+def cpu_baseline_plain(w, x_gpu, Omega):
+    """The oracle on the whole plain float64 workload (dense K, Nystrom, textbook
+    PCG), timed on the host, plus the GPU solution's error against its Cholesky
+    solve."""
+    import numpy as np
+    import oracle as o
+
+    t0 = time.perf_counter()
+    o.nyspcg_dense(w.X, w.B, w.lambdas, w.kind, w.sigma, Omega, tol=w.tol)
+    t_cpu = time.perf_counter() - t0
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    ref = o.direct_solve(K, w.B[:, 0], w.lambdas[0])
+    return {"value": t_cpu, "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": "the whole workload: dense K, Nystrom, textbook PCG (float64 NumPy)",
+            "rel_error_vs_cholesky": float(np.linalg.norm(x_gpu - ref) / np.linalg.norm(ref))}
+
+
+def grid_or_cg(args, nys, torch, ni, dev, T):
+    """grid_vs_fp32: the lambda-grid recipe (64 rhs x 8 lambdas) at a reduced n with the
+    mixed-precision product against plain float32 products, both to the float64-checked
+    tolerance.  cg_ratio: the float32 matrix-free workload (n = 2e5, d = 20) with NysPCG
+    against plain CG (no preconditioner), the ratio the paper reports for its ridge
+    problems (section "Large-Scale Ridge Regression with NysPCG")."""
+    def solve(w, X, B, Om0, prec, P_on, max_iters=1000):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = nys.build_preconditioner(X, Om0, w.kind, w.sigma, prec) if P_on else None
+        x, info, rc = nys.nyspcg_solve(X, B, w.lambdas, w.kind, w.sigma, P, tol=w.tol, max_iters=max_iters,
+                                       prec=prec, refine_every=0, refine_mode=1)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rel = [c["relres_true"] for c in info]
+        return {"seconds": round(t, 3), "status": rc, "max_iters": max(c["iters"] for c in info),
+                "sum_iters": sum(c["iters"] for c in info), "sum_refinements": sum(c["refinements"] for c in info),
+                "max_relres_true": max(rel), "accepted_fp64": rc == nys.OK and all(0 <= v <= w.tol for v in rel)}
+
+    seeds = [int(s) for s in args.seeds.split(",") if s.strip()] or [args.seed]
+    res = {}
+    for seed in seeds:
+        if args.workload == "grid_vs_fp32":
+            n = args.n if args.n != 1_000_000 else 200_000
+            w = ni.batched_lambda_grid(seed, n=n)
+        else:
+            w = ni.matrix_free_fp32(seed)
+        X, B = T(w.X), T(w.B)
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed + ni.OMEGA_SEED_OFFSET)
+        Om0 = torch.randn((w.n, w.r), generator=g, device=dev, dtype=torch.float64)
+        if args.workload == "grid_vs_fp32":
+            arms = (("f16x3_d10", nys.F16X3_D10, True), ("fp32", nys.FP32, True))
+        else:
+            arms = (("nyspcg", nys.FP32, True), ("cg", nys.FP32, False))
+        for name, prec, P_on in arms:
+            solve(w, X, B, Om0, prec, P_on, max_iters=10)                          # warm-up
+            r = solve(w, X, B, Om0, prec, P_on, max_iters=1000 if P_on else 20000)
+            res.setdefault(name, []).append(r)
+            phase(f"seed {seed} {name}: {r}")
+    names = list(res)
+    med = {k: statistics.median(r["seconds"] for r in v) for k, v in res.items()}
+    if args.workload == "grid_vs_fp32":
+        return {"metric": f"lambda-grid time-to-1e-6 float64 rel. residual, n={w.n} d=16, 64 rhs x 8 lambdas",
+                "value": round(med[names[0]], 3), "ms_per_step": round(med[names[0]] * 1e3, 1),
+                "dtype": "f16x3_d10", "steps": len(seeds),
+                "config": {"workload": "grid_vs_fp32", "n": w.n, "d": w.d, "rank": w.r, "tol": w.tol,
+                           "lambdas": [float(v) for v in w.lambdas]},
+                "runs": res, "median_s": med, "speedup_vs_fp32": round(med["fp32"] / med["f16x3_d10"], 3)}
+    return {"metric": "CG time / NysPCG time, n=2e5 d=20 float32 matrix-free, float64-checked 1e-6",
+            "value": round(med["cg"] / med["nyspcg"], 3), "unit": "ratio", "higher_is_better": True,
+            "ms_per_step": round(med["nyspcg"] * 1e3, 1), "dtype": "f32", "steps": len(seeds),
+            "config": {"workload": "cg_ratio", "n": w.n, "d": w.d, "rank": w.r, "tol": w.tol,
+                       "lambda": w.lambdas[0]},
+            "runs": res, "median_s": med}
 
 
 def log(args, *a):
@@ -272,7 +363,8 @@ def counted_traffic(prec_name: str, n: int, m: int):
 
 
 def time_kernel_matvec(nys, torch, X, sigma, m, prec, reps):
-    """Average duration of one kernel_matvec call (HIP events on the stream it runs on)."""
+    """Average duration of one kernel_matvec call, from HIP events recorded on the
+    stream the product is launched on (torch's current stream)."""
     g = torch.Generator(device=X.device)
     g.manual_seed(1234)
     dt = torch.float64 if prec == nys.FP64 else torch.float32
@@ -280,59 +372,79 @@ def time_kernel_matvec(nys, torch, X, sigma, m, prec, reps):
     out = torch.empty_like(V)
     nys.kernel_matvec(X, X, V, nys.RBF, sigma, prec, out=out)     # untimed first call
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
-    s.record()
+    s.record(stream)
     for _ in range(reps):
         nys.kernel_matvec(X, X, V, nys.RBF, sigma, prec, out=out)
-    e.record()
+    e.record(stream)
     torch.cuda.synchronize()
     t = s.elapsed_time(e) / 1e3 / reps
     del V, out
     return t
 
 
-def cpu_baseline(args, w, gpu_info):
-    """The oracle's K V (float64 NumPy) on a bounded row sample of the same workload,
-    scaled to a full time-to-solution estimate with the GPU run's product count."""
+def cpu_baseline(args, w, Xs_host, seconds, gpu_info):
+    """The oracle's float64 K V (NumPy) on a bounded row sample of the headline run:
+    V is the GPU's own solution (n x 512), so the same product also gives an
+    independent float64 residual estimate on the sampled rows.  The time is scaled to
+    a full time-to-solution estimate with the GPU run's product count."""
     import numpy as np
     import oracle as o
 
-    n, m = w.n, 512
-    rng = np.random.default_rng(7)
-    V = rng.standard_normal((n, m))
+    n, m = w.n, Xs_host.shape[1]
+    nrhs = w.B.shape[1]
     cores = os.cpu_count() or 1
+    rng = np.random.default_rng(11)
+    order = rng.permutation(n)
     rows = 8
     t0 = time.perf_counter()
-    o.kernel_matvec_rows(w.X[:rows], w.X, V, w.kind, w.sigma)
+    KX = [o.kernel_matvec_rows(w.X[order[:rows]], w.X, Xs_host, w.kind, w.sigma)]
     t_small = time.perf_counter() - t0
-    rows = max(rows, min(n, int(rows * args.cpu_seconds / max(t_small, 1e-3))))
-    t0 = time.perf_counter()
-    o.kernel_matvec_rows(w.X[:rows], w.X, V, w.kind, w.sigma)
+    more = max(0, min(n - rows, int(rows * seconds / max(t_small, 1e-3)) - rows))
+    if more:
+        KX.append(o.kernel_matvec_rows(w.X[order[rows:rows + more]], w.X, Xs_host, w.kind, w.sigma))
     t_rows = time.perf_counter() - t0
-    t_kv = t_rows * n / rows                       # one full 512-column K V, extrapolated
+    rows += more
+    sel = order[:rows]
+    KX = np.concatenate(KX, axis=0)
+    lam_col = np.array([w.lambdas[c // nrhs] for c in range(m)])
+    Bcol = w.B[sel][:, [c % nrhs for c in range(m)]]
+    res = Bcol - KX - lam_col * Xs_host[sel]
+    relres_rows = float((np.linalg.norm(res, axis=0) / np.linalg.norm(Bcol, axis=0)).max())
+    t_kv = t_rows * n / rows                       # one full m-column K V, extrapolated
     kv_equiv = gpu_info["kv_equivalents"]
     est = t_kv * kv_equiv
     return {
-        "value": est, "unit": "s", "cores": cores, "kind": "oracle",
-        "sample": (f"oracle float64 K(X[0:{rows}], X) V with V n x 512 on the n={n} point set took "
-                   f"{t_rows:.1f} s ({cores} host threads, {cpu_model()}); extrapolated x{n / rows:.0f} "
-                   f"to one full 512-column product ({t_kv:.0f} s) and x{kv_equiv:.1f} to the GPU run's "
-                   f"products (sum of column iterations and float64 refinements / 512)"),
-        "kernel_matvec_tflops": n * n * (2 * w.d + 2 * m) / t_kv / 1e12,
+        "value": round(est, 1), "unit": "s", "cores": cores, "kind": "oracle",
+        "sample": (f"oracle float64 K(X[S], X) V for {rows} random rows S of the n={n} point set with V the "
+                   f"GPU solution (n x {m}) took {t_rows:.1f} s ({cores} host threads, {cpu_model()}); "
+                   f"extrapolated x{n / rows:.0f} to one full {m}-column product ({t_kv:.0f} s) and "
+                   f"x{kv_equiv:.1f} to the GPU run's products (sum of column iterations plus 5 x float64 "
+                   f"refinements, / {m})"),
+        "kernel_matvec_tflops": round(n * n * (2 * w.d + 2 * m) / t_kv / 1e12, 4),
+        "oracle_sampled_rows_max_relres": relres_rows,
+        "rows": rows,
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.workload != "batched_lambda_grid":
-        run_other(args)
-        return
+def probes(nys, torch, dev):
+    """Sustained ceilings of the units the product uses (nys_peak_probe)."""
+    ws = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+    out = {
+        "bf16_mfma_tflops": nys.nys_peak_probe(nys.PROBE_BF16_MFMA, workspace=ws) / 1e12,
+        "f16_mfma_tflops": nys.nys_peak_probe(nys.PROBE_F16_MFMA, workspace=ws) / 1e12,
+        "f64_mfma_tflops": nys.nys_peak_probe(nys.PROBE_F64_MFMA, workspace=ws) / 1e12,
+        "exp2_f32_gexp_s": nys.nys_peak_probe(nys.PROBE_EXP2, workspace=ws) / 1e9,
+        "copy_gbs": nys.nys_peak_probe(nys.PROBE_COPY, 4, workspace=ws) / 1e9,
+    }
+    del ws
+    return {k: round(v, 1) for k, v in out.items()}
 
+
+def headline(args):
+    phase("loading torch and libnys")
     import numpy as np
     import torch
 
@@ -341,114 +453,158 @@ def main():
 
     nys.load()
     dev = torch.device("cuda:0")
-    w = ni.batched_lambda_grid(args.seed, n=args.n)
+    budget = args.budget_s
+    seeds = [int(s) for s in args.seeds.split(",") if s.strip()] or [args.seed]
+    prec = nys.PREC_BY_NAME[args.prec]
+
+    state = {}
+
+    def load_seed(seed):
+        if state.get("seed") == seed:
+            return state
+        state.clear()
+        w = ni.batched_lambda_grid(seed, n=args.n)
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed + ni.OMEGA_SEED_OFFSET)
+        state.update(seed=seed, w=w, X=torch.from_numpy(w.X).to(dev), B=torch.from_numpy(w.B).to(dev),
+                     Omega0=torch.randn((w.n, w.r), generator=g, device=dev, dtype=torch.float64))
+        return state
+
+    st = load_seed(seeds[0])
+    w, X = st["w"], st["X"]
     n, d, r = w.n, w.d, w.r
     nrhs, nlam = w.B.shape[1], len(w.lambdas)
     m = nrhs * nlam
-    # the smallest lambda (1e-7 n) lies below the three-term distance error (the operator
-    # would be indefinite); the ten-term split also removes the six-term split's structured
-    # error, which limits what one float64 refinement cycle gains for the small lambdas
-    prec = nys.PREC_BY_NAME[args.prec]
-    X = torch.from_numpy(w.X).to(dev)
-    B = torch.from_numpy(w.B).to(dev)
-    g = torch.Generator(device=dev)
-    g.manual_seed(args.seed + ni.OMEGA_SEED_OFFSET)
-    Omega0 = torch.randn((n, r), generator=g, device=dev, dtype=torch.float64)
-    Om = torch.empty_like(Omega0)
-    log(args, f"inputs ready: n={n} d={d} r={r} columns={m}")
+    phase(f"inputs ready: n={n} d={d} r={r} columns={m} ({nrhs} rhs x {nlam} lambdas) prec={args.prec}")
 
-    t_tune = 0.0
-    tiles = None
+    t_tune, tiles = 0.0, None
     if not args.no_autotune:
         t0 = time.perf_counter()
         tiles = nys.autotune(X, w.kind, w.sigma, prec, m, cache=args.tile_cache, n_rows=min(n, 262144))
         t_tune = time.perf_counter() - t0
-        log(args, f"autotune ({t_tune:.1f} s): " + ", ".join(f"{k}: {v['tm']}" for k, v in tiles.items()))
+        phase(f"autotune {t_tune:.1f} s: " + ", ".join(f"{k}: {v['tm']}" for k, v in tiles.items()))
     if args.kmv_only and args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log(args, "copy calibration: 1 GiB device-to-device copy done")
+        phase("copy calibration: 1 GiB device-to-device copy done")
         del src, dst
-    # ---- dominant kernel: the 512-column BF16X3 product (the solve's first product width)
+    ceilings = None
+    if not args.no_probe and not args.kmv_only:
+        ceilings = probes(nys, torch, dev)
+        phase(f"ceiling probes: {ceilings}")
+    # ---- dominant kernel: the m-column product (the solve's first product width)
     t_kmv = time_kernel_matvec(nys, torch, X, w.sigma, m, prec, args.kmv_reps)
     flops = n * n * (2 * d + 2 * m)
     kmv_tflops = flops / t_kmv / 1e12
-    log(args, f"kernel_matvec m={m}: {t_kmv * 1e3:.1f} ms, {kmv_tflops:.1f} TFLOP/s")
+    phase(f"kernel_matvec m={m}: {t_kmv * 1e3:.1f} ms, {kmv_tflops:.1f} TFLOP/s")
     t_kmv1 = time_kernel_matvec(nys, torch, X, w.sigma, 1, prec, args.kmv_reps)
-    log(args, f"kernel_matvec m=1: {t_kmv1 * 1e3:.1f} ms")
+    phase(f"kernel_matvec m=1: {t_kmv1 * 1e3:.1f} ms")
     if args.kmv_only:
         res = {"kernel_matvec_ms": t_kmv * 1e3, "tflops": kmv_tflops, "m1_ms": t_kmv1 * 1e3}
         for mc in [int(c) for c in args.kmv_fp64.split(",") if c.strip()]:
             t64 = time_kernel_matvec(nys, torch, X, w.sigma, mc, nys.FP64, args.kmv_reps)
-            log(args, f"float64 kernel_matvec m={mc}: {t64 * 1e3:.1f} ms")
+            phase(f"float64 kernel_matvec m={mc}: {t64 * 1e3:.1f} ms")
             res[f"fp64_m{mc}_ms"] = t64 * 1e3
-        print(json.dumps(res))
+        print(json.dumps(res), flush=True)
         return
 
     ws = torch.empty(nys.nys_workspace_bytes(nys.OP_SOLVE, n, 0, d, r, m, prec), dtype=torch.uint8, device=dev)
 
-    def step(max_iters):
-        Om.copy_(Omega0)
+    def step(st, max_iters, B=None, lambdas=None):
+        Xd = st["X"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Y = nys.nys_sketch(X, Om, w.kind, w.sigma, prec)
+        Y, Q = nys.nys_sketch(Xd, st["Omega0"], w.kind, w.sigma, prec)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        P = nys.nys_precond_build(Y, Om, prec, with_fp32=True)
-        del Y
+        P = nys.nys_precond_build(Y, Q, prec, with_fp32=True)
+        del Y, Q
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        Xs, info, rc = nys.nyspcg_solve(X, B, w.lambdas, w.kind, w.sigma, P, tol=w.tol, max_iters=max_iters,
-                                        prec=prec, refine_every=args.refine_every, refine_mode=args.refine_mode,
-                                        refine_reduction=args.refine_reduction,
-                                        workspace=ws)
+        Xs, info, rc = nys.nyspcg_solve(Xd, st["B"] if B is None else B, w.lambdas if lambdas is None else lambdas,
+                                        w.kind, w.sigma, P, tol=w.tol, max_iters=max_iters, prec=prec,
+                                        refine_every=args.refine_every, refine_mode=args.refine_mode,
+                                        refine_reduction=args.refine_reduction, workspace=ws)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         return Xs, info, rc, P, (t1 - t0, t2 - t1, t3 - t2, t3 - t0)
 
-    for _ in range(args.warmup):
-        step(10)
-        log(args, "warmup done")
-    times, phases, last = [], [], None
-    for _ in range(args.steps):
-        Xs, info, rc, P, ph = step(1000)
-        times.append(ph[3])
-        phases.append(ph)
-        last = (Xs, info, rc, P)
-        log(args, f"step: sketch {ph[0]:.2f}s build {ph[1]:.2f}s solve {ph[2]:.2f}s total {ph[3]:.2f}s rc={rc}")
-    Xs, info, rc, P = last
+    n_warm = 0
+    if args.warmup > 0:
+        step(st, 10)
+        n_warm = 1
+        phase("warm-up step (10 iterations) done")
+    # time the report needs after the last step: single-RHS solve, acceptance, oracle sample
+    reserve = (0 if args.no_m1 else 25.0) + (0 if args.no_cpu else args.cpu_seconds + 10.0) + 10.0
+    runs = []
+    for k in range(max(1, args.steps)):
+        if k > 0:
+            worst = max(rn["phases"][3] for rn in runs)
+            if elapsed() + 1.05 * worst + reserve > budget:
+                phase(f"budget: next step would end past {budget:.0f} s; stopping after {k} timed step(s)")
+                break
+        seed = seeds[k % len(seeds)]
+        st = load_seed(seed)
+        Xs, info, rc, P, ph = step(st, 1000)
+        rel_true = [c["relres_true"] for c in info]
+        runs.append({"seed": seed, "phases": ph, "rc": rc, "info": info, "rank": P.rank, "nu": P.nu,
+                     "accepted": rc == nys.OK and all(0 <= v <= w.tol for v in rel_true),
+                     "max_relres_true": max(rel_true)})
+        phase(f"timed step {k + 1} (seed {seed}): sketch {ph[0]:.2f} s, build {ph[1]:.2f} s, solve {ph[2]:.2f} s, "
+              f"total {ph[3]:.2f} s, rc={rc}, max true relres {max(rel_true):.3e}")
+        del P
+    last = runs[-1]
+    st = load_seed(last["seed"])
+    w = st["w"]
+    info = last["info"]
+    times = [rn["phases"][3] for rn in runs]
     t_step = statistics.median(times)
-
-    # ---- acceptance, after the timer: every column's float64 true relative residual
-    rel_true = [c["relres_true"] for c in info]
-    ok = all(0 <= v <= w.tol for v in rel_true) and rc == nys.OK
     iters = [c["iters"] for c in info]
     refs = [c["refinements"] for c in info]
-    # independent check on 8192 sampled rows: r_i = b_i - (K x)_i - lambda x_i in float64
-    # (|r_S| / |b_S| estimates each column's relative residual to a few per cent)
+    per_lambda = {f"{w.lambdas[l]:.3g}": max(iters[l * nrhs:(l + 1) * nrhs]) for l in range(nlam)}
+
+    # ---- independent acceptance check (after the timer) on 8192 sampled rows:
+    # r_S = b_S - (K x)_S - lambda x_S with the float64 product
     rows = torch.from_numpy(np.sort(np.random.default_rng(3).choice(n, min(n, 8192), replace=False))).to(dev)
-    KX = nys.kernel_matvec(X[rows].contiguous(), X, Xs, w.kind, w.sigma, nys.FP64)
+    KX = nys.kernel_matvec(st["X"][rows].contiguous(), st["X"], Xs, w.kind, w.sigma, nys.FP64)
     lam_col = torch.tensor([w.lambdas[c // nrhs] for c in range(m)], dtype=torch.float64, device=dev)
-    Bcol = B[:, [c % nrhs for c in range(m)]]
+    Bcol = st["B"][:, [c % nrhs for c in range(m)]]
     res = Bcol[rows] - KX - lam_col * Xs[rows]
     sampled = (res.norm(dim=0) / Bcol[rows].norm(dim=0)).max().item()
-    per_lambda = {f"{w.lambdas[l]:.3g}": max(iters[l * nrhs:(l + 1) * nrhs]) for l in range(nlam)}
-    kv_equiv = (sum(iters) + sum(refs) * 5) / m   # a float64 column product costs ~5 BF16X3 ones
-    gpu_info = {"kv_equivalents": kv_equiv}
+    del KX, res, Bcol
+    phase(f"sampled-row float64 check: max relres {sampled:.3e}")
 
+    # ---- single right-hand side (m = 1) at lambda = 1e-3 n: sketch + build + solve
+    single = None
+    if not args.no_m1 and elapsed() + 30.0 + (0 if args.no_cpu else args.cpu_seconds + 10.0) < budget:
+        b1 = st["B"][:, :1].contiguous()
+        _, info1, rc1, P1, ph1 = step(st, 1000, B=b1, lambdas=[w.lambdas[-1]])
+        single = {"lambda": float(w.lambdas[-1]), "seconds": round(ph1[3], 3),
+                  "phases_s": {"sketch": round(ph1[0], 3), "build": round(ph1[1], 3), "solve": round(ph1[2], 3)},
+                  "iters": info1[0]["iters"], "refinements": info1[0]["refinements"],
+                  "relres_true": info1[0]["relres_true"], "status": rc1}
+        del P1
+        phase(f"single right-hand side: {ph1[3]:.2f} s, {info1[0]['iters']} iterations, "
+              f"true relres {info1[0]['relres_true']:.3e}")
+
+    kv_equiv = (sum(iters) + sum(refs) * 5) / m   # a float64 column product costs ~5 low-precision ones
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args, w, gpu_info)
+        secs = max(2.0, min(args.cpu_seconds, budget - elapsed() - 10.0))
+        phase(f"oracle sample on the host ({secs:.0f} s target)")
+        cpu = cpu_baseline(args, w, Xs.cpu().numpy(), secs, {"kv_equivalents": kv_equiv})
+        phase(f"oracle sample: {cpu['rows']} rows, sampled-row relres {cpu['oracle_sampled_rows_max_relres']:.3e}")
 
+    three = PEAK_BF16_TFLOPS / 3.0
     out = {
         "metric": METRIC,
         "value": round(t_step, 3),
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": len(runs),
+        "warmup": n_warm,
         "ms_per_step": round(t_step * 1e3, 1),
         "higher_is_better": False,
         "scaling": "weak",
@@ -462,6 +618,10 @@ def main():
             "precision": f"{args.prec} K V, fp32 CG, fp64 residual refinement",
             "refine_every": args.refine_every, "refine_mode": args.refine_mode,
         },
+        "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": budget,
+        "seeds": [rn["seed"] for rn in runs],
+        "step_s": {"median": round(t_step, 3), "min": round(min(times), 3), "max": round(max(times), 3),
+                   "all": [round(t, 3) for t in times]},
         "tiles": {"autotune_s": round(t_tune, 1), "widths": {k: v["tm"] for k, v in (tiles or {}).items()}},
         "kernel_matvec_tflops": round(kmv_tflops, 1),
         "kernel_matvec": {"m": m, "ms": round(t_kmv * 1e3, 2), "tflops": round(kmv_tflops, 1),
@@ -470,20 +630,39 @@ def main():
         "roofline": {
             "bound": "mfma",
             "achieved": round(kmv_tflops, 1),
-            "peak": round(PEAK_BF16_TFLOPS / 3.0, 1),
+            "peak": PEAK_BF16_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(kmv_tflops / (PEAK_BF16_TFLOPS / 3.0), 4),
+            "frac": round(kmv_tflops / PEAK_BF16_TFLOPS, 4),
             "traffic": counted_traffic(args.prec, n, m),
+            "three_product_roof": {"peak": round(three, 1), "frac": round(kmv_tflops / three, 4),
+                                   "note": "each multiply of the split product is three MFMA products"},
+            "measured_ceilings": ceilings,
         },
-        "phases_s": {"sketch": round(phases[-1][0], 3), "build": round(phases[-1][1], 3),
-                     "solve": round(phases[-1][2], 3)},
-        "solve": {"status": rc, "accepted_fp64": ok, "max_relres_true": max(rel_true),
+        "phases_s": {"sketch": round(last["phases"][0], 3), "build": round(last["phases"][1], 3),
+                     "solve": round(last["phases"][2], 3)},
+        "solve": {"status": last["rc"], "accepted_fp64": all(rn["accepted"] for rn in runs),
+                  "max_relres_true": max(rn["max_relres_true"] for rn in runs),
                   "sampled_rows_max_relres": sampled, "max_iters_per_lambda": per_lambda,
-                  "sum_column_iters": sum(iters), "sum_refinements": sum(refs), "rank": P.rank, "nu": P.nu},
+                  "sum_column_iters": sum(iters), "sum_refinements": sum(refs), "rank": last["rank"],
+                  "nu": last["nu"]},
+        "single_rhs": single,
         "cpu_baseline": cpu,
         "device": device_label(torch),
+        "wall_s": round(elapsed(), 1),
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.workload != "batched_lambda_grid":
+        run_other(args)
+        return
+    headline(args)
 
 
 if __name__ == "__main__":

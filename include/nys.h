@@ -94,7 +94,9 @@ typedef enum {
   NYS_OP_PRECOND_APPLY = 3,
   NYS_OP_SOLVE = 4,
   NYS_OP_BACKWARD = 5,
-  NYS_OP_AUTOTUNE = 6
+  NYS_OP_AUTOTUNE = 6,
+  NYS_OP_KERNEL_DOT = 7,
+  NYS_OP_PRECOND_ADAPTIVE = 8
 } nys_op;
 
 /* Kernel function: kind (nys_kind) and bandwidth sigma > 0. */
@@ -104,9 +106,11 @@ typedef struct {
   double sigma;
 } nys_kernel;
 
-/* Nystrom preconditioner P = U diag(lam_hat) U^T + lambda I (damping mode
- * "non_adaptive" with base damping lambda, table tab:rlaopt-nystrom-config).
- * The caller allocates the buffers; nys_precond_build fills them.
+/* Nystrom preconditioner P = U diag(lam_hat) U^T + (lambda + shift) I, with lambda the
+ * regularisation of the column being solved (the base damping) and shift 0 for the
+ * damping mode "non_adaptive" or the smallest retained lam_hat for "adaptive" (table
+ * tab:rlaopt-nystrom-config).  The caller allocates the buffers; nys_precond_build
+ * (shift 0) or nys_precond_adaptive fills them.
  *    n        number of points (rows of U)
  *    r        sketch size = columns of U (rank_init of the paper's NystromConfig)
  *    rank     out: columns of U kept (those with sigma_i^2 > 1e-14 sigma_1^2);
@@ -116,6 +120,8 @@ typedef struct {
  *             apply itself always works from U in float64)
  *    lam_hat  device, r float64, descending, >= 0
  *    nu       out: the shift used by the stabilised approximation
+ *    shift    extra damping added to every column's lambda in the apply (out of
+ *             nys_precond_build: 0; of nys_precond_adaptive: per damping mode)
  */
 typedef struct {
   int64_t n;
@@ -125,7 +131,31 @@ typedef struct {
   float *U32;
   double *lam_hat;
   double nu;
+  double shift;
 } nys_precond;
+
+/* Damping modes of table tab:rlaopt-nystrom-config. */
+#define NYS_DAMPING_NON_ADAPTIVE 0   /* damping = base damping (lambda) */
+#define NYS_DAMPING_ADAPTIVE     1   /* damping = lambda + smallest retained lam_hat */
+
+/* Nystrom configuration with rank adaptation (NystromConfig of table
+ * tab:rlaopt-nystrom-config).
+ *    rank_init        initial sketch size l (>= 1)
+ *    rank_max         largest l (0: rank_init, i.e. no adaptation)
+ *    num_power_iters  power iterations of the error estimate (paper default 10)
+ *    damping_mode     NYS_DAMPING_ADAPTIVE (paper default) or NYS_DAMPING_NON_ADAPTIVE
+ *    error_tolerance  stop when the estimate of |K - K_hat|_2 is at most
+ *                     error_tolerance * lam_hat_1 (paper default 1e-2)
+ *    seed             the test matrix is nys_test_matrix(seed, n, rank_max); the power
+ *                     iteration starts from nys_test_matrix(seed + 1, n, 1) */
+typedef struct {
+  int32_t rank_init;
+  int32_t rank_max;
+  int32_t num_power_iters;
+  int32_t damping_mode;
+  double error_tolerance;
+  uint64_t seed;
+} nys_nystrom_config;
 
 /* PCG options (PCGStoppingCriteria, table tab:rlaopt-pcg-stopping, plus the
  * precision controls of this library).
@@ -191,6 +221,8 @@ typedef struct {
  *   SOLVE:         n, d, r (0 if no preconditioner), m = nlam * nrhs, prec
  *   BACKWARD:      n, d, r, prec
  *   AUTOTUNE:      n = n_rows, n2 = n, d, m, prec
+ *   KERNEL_DOT:    n = nr, n2 = nc, d
+ *   PRECOND_ADAPTIVE: n, d, r = rank_max, prec
  * Returns NYS_OK and *bytes, or NYS_EINVAL. */
 int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_t r, int32_t m,
                             int32_t prec, size_t *bytes);
@@ -206,23 +238,56 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
  *    V    device nc x m, float64 if prec == NYS_FP64 else float32
  *    Out  device nr x m, same type as V; not read when beta == 0
  * Coordinates are centred on the column mean of Xc (distances are unchanged).
- * d must be <= 62 (FP32/FP64) or <= 82 (BF16X3). */
+ * d must be <= 62 (FP32/FP64), <= 82 (BF16X3), <= 41 (BF16X3_D6) or <= 24 (the
+ * ten-term splits).  The stream is synchronised once, after the points are packed
+ * and before the product is enqueued, to read the packing's finiteness check: a NaN
+ * or Inf coordinate in Xr or Xc returns NYS_ENUMERIC. */
 int32_t kernel_matvec(nys_kernel k, int32_t deriv, int32_t prec,
                       const double *Xr, int64_t nr, const double *Xc, int64_t nc, int32_t d,
                       const void *V, int32_t m, void *Out, double alpha, double beta,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* kernel_dot: *out = u^T K(Xr, Xc) v, or with deriv = 1 u^T (dK/dsigma) v, in
+ * float64: the scalar contractions of the kernel with two vectors that the
+ * gradient of a validation loss through the solution needs (eq. rlaopt-bilevel:
+ * the explicit sigma-derivative e^T (dK_vt/dsigma) x of the prediction K_vt x).
+ *    Xr  device float64 nr x d;  Xc  device float64 nc x d (Xr == Xc with nr == nc
+ *        marks a symmetric product, K_ii = 1 exactly)
+ *    u   device float64 nr;  v  device float64 nc
+ *    out HOST, one double
+ * Synchronises the stream.  NaN or Inf in Xr or Xc: NYS_ENUMERIC. */
+int32_t kernel_dot(nys_kernel k, int32_t deriv, const double *Xr, int64_t nr, const double *Xc, int64_t nc,
+                   int32_t d, const double *u, const double *v, double *out, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* nys_test_matrix: Omega (n x r, device float64, row-major) filled with standard
+ * normals as a pure function of (seed, element index): Philox4x32 with 10 rounds
+ * (Salmon et al., SC 2011) on the counter (b mod 2^32, b / 2^32, 0, 0) with key
+ * (seed mod 2^32, seed / 2^32) for the element pair b = e / 2, two 53-bit uniforms
+ * u, v from the output words (w0, w1) and (w2, w3), and the Box-Muller pair
+ * sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v) (cosine for even e, sine for odd e).
+ * Any row range of Omega can therefore be drawn independently.  This is the
+ * Gaussian test matrix of the randomized Nystrom sketch (the method the paper
+ * cites for its preconditioner).  Enqueued on stream; no synchronisation. */
+int32_t nys_test_matrix(uint64_t seed, int64_t n, int32_t r, double *Omega, void *stream);
+
 /* nys_sketch: the sketch Y = K Q of the randomized Nystrom approximation (the
  * preconditioner the paper cites in "Related Work", configured by table
  * tab:rlaopt-nystrom-config).
  *    X      device float64 n x d
- *    Omega  device float64 n x r, in: standard Gaussian test matrix (drawn by
- *           the caller); out: overwritten by Q, its orthonormalisation
- *           (Q = Omega L^{-T}, L L^T = Omega^T Omega)
+ *    Omega  device float64 n x r, the standard Gaussian test matrix (read only), or
+ *           NULL: drawn on the device from `seed` as nys_test_matrix does
+ *    seed   used only when Omega is NULL
+ *    Q      device float64 n x r, out: the orthonormalised test matrix
+ *           Q = Omega L^{-T}, L L^T = Omega^T Omega (Cholesky QR); must not
+ *           overlap Omega.  nys_precond_build takes it together with Y.
  *    Y      device float64 n x r, out: K Q computed with the precision prec
- * Requires 1 <= r <= n and r <= 1024. */
+ * Requires 1 <= r <= n and r <= 1024.  NYS_ENOTPD if Omega^T Omega is not
+ * positive definite (rank-deficient or non-finite Omega); NYS_ENUMERIC for NaN or
+ * Inf in X.  Synchronises the stream. */
 int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32_t d,
-                   double *Omega, int32_t r, double *Y, void *ws, size_t ws_bytes, void *stream);
+                   const double *Omega, uint64_t seed, int32_t r, double *Q, double *Y, void *ws,
+                   size_t ws_bytes, void *stream);
 
 /* nys_precond_build: stabilised fixed-rank Nystrom approximation from the
  * sketch, all in float64 on the device:
@@ -237,9 +302,26 @@ int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32
 int32_t nys_precond_build(const double *Y, const double *Q, int64_t n, int32_t r, int32_t sketch_prec,
                           nys_precond *P, void *ws, size_t ws_bytes, void *stream);
 
+/* nys_precond_adaptive: the Nystrom preconditioner with rank adaptation and the damping
+ * mode of cfg (table tab:rlaopt-nystrom-config).  The paper lists the parameters but
+ * not the loop; this one starts at l = rank_init and, while the power-iteration
+ * estimate of |K - K_hat|_2 exceeds error_tolerance * lam_hat_1 and l < rank_max,
+ * doubles l (capped at rank_max).  Growing l applies K only to the test-matrix columns
+ * added: the sketch K Omega of the first l columns is orthonormalised by Cholesky QR
+ * (Q = Omega_l L^-T, Y = (K Omega_l) L^-T) and built as nys_precond_build does.  The
+ * kernel products (sketch and power iteration) run at precision prec.
+ *    P       in: n, r = rank_max, buffers U (n x rank_max), U32 (nullable), lam_hat
+ *            (rank_max); out: r = the final l, U as n x l (row stride l) at the start
+ *            of the buffer, lam_hat (zero past l), rank, nu, shift
+ *    err_out HOST, nullable: the last error estimate
+ * NYS_ENOTPD / NYS_ENUMERIC as nys_sketch and nys_precond_build. */
+int32_t nys_precond_adaptive(nys_kernel k, int32_t prec, const double *X, int64_t n, int32_t d,
+                             const nys_nystrom_config *cfg, nys_precond *P, double *err_out, void *ws,
+                             size_t ws_bytes, void *stream);
+
 /* nys_precond_apply: Z = P_c^{-1} R for every column c, with
- * P_c = U diag(lam_hat) U^T + lambdas[c] I, through the closed form
- * P_c^{-1} = U diag(1/(lam_hat + lambda_c)) U^T + (I - U U^T) / lambda_c.
+ * P_c = U diag(lam_hat) U^T + rho_c I, rho_c = lambdas[c] + P->shift, through the closed form
+ * P_c^{-1} = U diag(1/(lam_hat + rho_c)) U^T + (I - U U^T) / rho_c.
  *    lambdas  device float64, m values (lambda_c > 0)
  *    R, Z     device n x m; float64 if prec == NYS_FP64, else float32
  * The arithmetic is float64 in every case (float32 vectors are rounded once on
@@ -281,7 +363,6 @@ int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, dou
                         double *dL_dsigma, nys_col_info *info, void *ws, size_t ws_bytes,
                         void *stream);
 
-/* Thread-local description of the last non-zero status ("" if none). */
 /* ---- tile autotuner -------------------------------------------------------
  * The batched solve runs the kernel product at many column counts (columns
  * leave as they converge).  nys_autotune times kernel_matvec(X[0:n_rows], X)
@@ -322,6 +403,27 @@ void nys_clear_tiles(void);
  * of range or a null output. */
 int32_t nys_plan_chunks(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *tm, int32_t *tail_tm);
 
+/* ---- ceiling probes --------------------------------------------------------
+ * nys_peak_probe times one synthetic kernel that keeps a single unit of the GPU
+ * busy, so that the rates of the kernel product can be set against what the chip
+ * sustains as well as against its data sheet.  It is measurement support, not
+ * part of the method.
+ *    which  0: bf16 MFMA (v_mfma_f32_16x16x32_bf16), flop/s
+ *           1: fp16 MFMA (v_mfma_f32_16x16x32_f16), flop/s
+ *           2: float64 MFMA (v_mfma_f64_16x16x4f64), flop/s
+ *           3: float32 exp2 (v_exp_f32), exponentials/s
+ *           4: device copy over the workspace (first half to second half),
+ *              bytes read + written per second
+ *    iters  loop length per lane (0: about 50-100 ms per launch); for which = 4
+ *           the number of timed copies (0: one)
+ *    rate   HOST, out
+ * ws: device scratch, at least 2 MiB (which = 4 copies ws_bytes / 2 bytes, so a
+ * large workspace measures HBM rather than cache).  One untimed launch precedes the
+ * timed one(s) on `stream`; synchronises the stream.  NYS_EINVAL for which outside
+ * 0..4 or a null pointer, NYS_ENOMEM for a smaller workspace. */
+int32_t nys_peak_probe(int32_t which, int32_t iters, double *rate, void *ws, size_t ws_bytes, void *stream);
+
+/* Thread-local description of the last non-zero status ("" if none). */
 const char *nys_last_error(void);
 
 /* Library version string. */

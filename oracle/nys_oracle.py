@@ -173,18 +173,73 @@ def nystrom_matrix(U: np.ndarray, lam_hat: np.ndarray) -> np.ndarray:
     return (U * lam_hat) @ U.T
 
 
-def precond_apply(U: np.ndarray, lam_hat: np.ndarray, lam, R: np.ndarray) -> np.ndarray:
-    """P^{-1} R for P = U diag(lam_hat) U^T + lam I, by its closed-form inverse
-    P^{-1} = U diag(1 / (lam_hat + lam)) U^T + (I - U U^T) / lam.
-    lam may be a scalar or one value per column of R."""
+def precond_apply(U: np.ndarray, lam_hat: np.ndarray, lam, R: np.ndarray, shift: float = 0.0) -> np.ndarray:
+    """P^{-1} R for P = U diag(lam_hat) U^T + rho I, rho = lam + shift, by its closed-form
+    inverse P^{-1} = U diag(1 / (lam_hat + rho)) U^T + (I - U U^T) / rho.
+    lam may be a scalar or one value per column of R.  shift is 0 for the damping mode
+    "non_adaptive" and the smallest retained lam_hat for "adaptive" (table
+    tab:rlaopt-nystrom-config; see damping_shift)."""
     R = np.asarray(R, dtype=np.float64)
     one = R.ndim == 1
     if one:
         R = R[:, None]
-    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (R.shape[1],))
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (R.shape[1],)) + float(shift)
     W = U.T @ R
     Z = U @ (W / (lam_hat[:, None] + lam[None, :])) + (R - U @ W) / lam[None, :]
     return Z[:, 0] if one else Z
+
+
+# ---------------------------------------------------------------------------
+# Rank adaptation and damping modes (table tab:rlaopt-nystrom-config)
+# ---------------------------------------------------------------------------
+
+def power_error(apply_K, U: np.ndarray, lam_hat: np.ndarray, v0: np.ndarray, iters: int) -> float:
+    """Estimate of |K - K_hat|_2 by `iters` power iterations on E = K - U diag(lam_hat) U^T
+    (the error estimation of rank adaptation, num_power_iters in table
+    tab:rlaopt-nystrom-config): v = v0 / |v0|, then per iteration w = E v, the Rayleigh
+    quotient v^T w, and v = w / |w|.  Returns the last Rayleigh quotient."""
+    v = np.asarray(v0, dtype=np.float64).reshape(-1)
+    v = v / np.linalg.norm(v)
+    est = 0.0
+    for _ in range(iters):
+        w = np.asarray(apply_K(v[:, None]), dtype=np.float64).reshape(-1) - U @ (lam_hat * (U.T @ v))
+        est = float(v @ w)
+        nw = float(np.linalg.norm(w))
+        if nw == 0.0:
+            break
+        v = w / nw
+    return est
+
+
+def nystrom_adaptive(apply_K, Omega_full: np.ndarray, rank_init: int, rank_max: int | None,
+                     num_power_iters: int, error_tolerance: float, v0: np.ndarray):
+    """Nystrom approximation with rank adaptation (table tab:rlaopt-nystrom-config:
+    rank_init, rank_max, num_power_iters, error_tolerance).  The paper gives the
+    parameters but not the loop; the reading taken here: start at rank_init, build the
+    stabilised approximation from the first l columns of one test matrix, estimate
+    |K - K_hat|_2 with num_power_iters power iterations, and stop when the estimate is
+    at most error_tolerance times the largest approximate eigenvalue or l has reached
+    rank_max (rank_max None: rank_init); otherwise double l (capped at rank_max).
+    Returns (U, lam_hat, nu, l, error estimate)."""
+    rmax = rank_init if rank_max is None else rank_max
+    l = min(rank_init, rmax)
+    while True:
+        U, lam_hat, nu = nystrom(apply_K, Omega_full[:, :l])
+        err = power_error(apply_K, U, lam_hat, v0, num_power_iters)
+        if err <= error_tolerance * lam_hat[0] or l >= rmax:
+            return U, lam_hat, nu, l, err
+        l = min(2 * l, rmax)
+
+
+def damping_shift(lam_hat: np.ndarray, mode: str) -> float:
+    """Extra damping of the preconditioner: "adaptive" adds the smallest retained
+    approximate eigenvalue to the base damping, "non_adaptive" adds nothing (table
+    tab:rlaopt-nystrom-config)."""
+    if mode == "adaptive":
+        return float(lam_hat[-1])
+    if mode == "non_adaptive":
+        return 0.0
+    raise ValueError("damping mode must be 'adaptive' or 'non_adaptive'")
 
 
 # ---------------------------------------------------------------------------

@@ -24,11 +24,13 @@ PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16X3_D6: "bf16x3_d
 PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
-OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BACKWARD, OP_AUTOTUNE = range(7)
+(OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BACKWARD, OP_AUTOTUNE,
+ OP_KERNEL_DOT, OP_PRECOND_ADAPTIVE) = range(9)
 
-EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "nys_sketch", "nys_precond_build",
+EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "kernel_dot", "nys_test_matrix", "nys_sketch", "nys_precond_build",
+           "nys_precond_adaptive",
            "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_autotune", "nys_set_tile",
-           "nys_clear_tiles", "nys_plan_chunks", "nys_last_error", "nys_version")
+           "nys_clear_tiles", "nys_plan_chunks", "nys_peak_probe", "nys_last_error", "nys_version")
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -39,7 +41,15 @@ class NysKernel(ctypes.Structure):
 
 class NysPrecondC(ctypes.Structure):
     _fields_ = [("n", c_i64), ("r", c_i32), ("rank", c_i32), ("U", c_vp), ("U32", c_vp),
-                ("lam_hat", c_vp), ("nu", c_f64)]
+                ("lam_hat", c_vp), ("nu", c_f64), ("shift", c_f64)]
+
+
+DAMPING_NON_ADAPTIVE, DAMPING_ADAPTIVE = 0, 1
+
+
+class NysNystromConfig(ctypes.Structure):
+    _fields_ = [("rank_init", c_i32), ("rank_max", c_i32), ("num_power_iters", c_i32), ("damping_mode", c_i32),
+                ("error_tolerance", c_f64), ("seed", ctypes.c_uint64)]
 
 
 class NysPCGOpts(ctypes.Structure):
@@ -82,9 +92,15 @@ def load(path: str | None = None):
     lib.nys_workspace_bytes.argtypes = [c_i32, c_i64, c_i64, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]
     lib.kernel_matvec.argtypes = [NysKernel, c_i32, c_i32, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp,
                                   c_f64, c_f64, c_vp, c_sz, c_vp]
-    lib.nys_sketch.argtypes = [NysKernel, c_i32, c_vp, c_i64, c_i32, c_vp, c_i32, c_vp, c_vp, c_sz, c_vp]
+    lib.kernel_dot.argtypes = [NysKernel, c_i32, c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_vp, ctypes.POINTER(c_f64),
+                               c_vp, c_sz, c_vp]
+    lib.nys_test_matrix.argtypes = [ctypes.c_uint64, c_i64, c_i32, c_vp, c_vp]
+    lib.nys_sketch.argtypes = [NysKernel, c_i32, c_vp, c_i64, c_i32, c_vp, ctypes.c_uint64, c_i32, c_vp, c_vp, c_vp,
+                               c_sz, c_vp]
     lib.nys_precond_build.argtypes = [c_vp, c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(NysPrecondC), c_vp, c_sz, c_vp]
     lib.nys_precond_apply.argtypes = [ctypes.POINTER(NysPrecondC), c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_sz, c_vp]
+    lib.nys_precond_adaptive.argtypes = [NysKernel, c_i32, c_vp, c_i64, c_i32, ctypes.POINTER(NysNystromConfig),
+                                         ctypes.POINTER(NysPrecondC), ctypes.POINTER(c_f64), c_vp, c_sz, c_vp]
     lib.nyspcg_solve.argtypes = [NysKernel, c_vp, c_i64, c_i32, c_vp, c_i32, ctypes.POINTER(c_f64), c_i32,
                                  ctypes.POINTER(NysPrecondC), ctypes.POINTER(NysPCGOpts), c_vp,
                                  ctypes.POINTER(NysColInfo), c_vp, c_sz, c_vp]
@@ -97,8 +113,10 @@ def load(path: str | None = None):
     lib.nys_clear_tiles.argtypes = []
     lib.nys_clear_tiles.restype = None
     lib.nys_plan_chunks.argtypes = [c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
-    for name in ("kernel_matvec", "nys_sketch", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
-                 "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile", "nys_plan_chunks"):
+    lib.nys_peak_probe.argtypes = [c_i32, c_i32, ctypes.POINTER(c_f64), c_vp, c_sz, c_vp]
+    for name in ("kernel_matvec", "kernel_dot", "nys_test_matrix", "nys_sketch", "nys_precond_adaptive", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
+                 "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile", "nys_plan_chunks",
+                 "nys_peak_probe"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     _lib_file = p
@@ -194,12 +212,14 @@ def kernel_matvec(Xr, Xc, V, kind: int, sigma: float, prec: int = FP64, deriv: i
 
 @dataclass
 class Preconditioner:
-    """Nystrom preconditioner P = U diag(lam_hat) U^T + lambda I (buffers on the device)."""
+    """Nystrom preconditioner P = U diag(lam_hat) U^T + (lambda + shift) I (buffers on the
+    device; shift is the adaptive damping, 0 for the non-adaptive mode)."""
     U: torch.Tensor
     U32: torch.Tensor | None
     lam_hat: torch.Tensor
     rank: int = 0
     nu: float = 0.0
+    shift: float = 0.0
 
     @property
     def n(self) -> int:
@@ -212,24 +232,59 @@ class Preconditioner:
     def c_struct(self) -> NysPrecondC:
         return NysPrecondC(self.n, self.r, self.rank, self.U.data_ptr(),
                            self.U32.data_ptr() if self.U32 is not None else None,
-                           self.lam_hat.data_ptr(), self.nu)
+                           self.lam_hat.data_ptr(), self.nu, self.shift)
 
 
-def nys_sketch(X, Omega, kind: int, sigma: float, prec: int = FP64):
-    """Y = K Q with Q the orthonormalised Omega (Omega is overwritten by Q)."""
+def kernel_dot(Xr, Xc, u, v, kind: int, sigma: float, deriv: int = 0) -> float:
+    """u^T K(Xr, Xc) v (deriv=1: u^T (dK/dsigma) v) in float64; u, v 1-D float64."""
+    lib = load()
+    _need_cuda(Xr, torch.float64, "Xr")
+    _need_cuda(Xc, torch.float64, "Xc")
+    u1, v1 = u.reshape(-1), v.reshape(-1)
+    _need_cuda(u1, torch.float64, "u")
+    _need_cuda(v1, torch.float64, "v")
+    nr, d = Xr.shape
+    nc = Xc.shape[0]
+    if Xc.shape[1] != d or u1.numel() != nr or v1.numel() != nc:
+        raise ValueError("shape mismatch")
+    ws = _workspace(nys_workspace_bytes(OP_KERNEL_DOT, nr, nc, d), Xr.device)
+    out = c_f64(0.0)
+    _check(lib.kernel_dot(NysKernel(kind, 0, float(sigma)), int(deriv), Xr.data_ptr(), nr, Xc.data_ptr(), nc, d,
+                          u1.data_ptr(), v1.data_ptr(), ctypes.byref(out), ws.data_ptr(), ws.numel(), _stream()),
+           allow_not_converged=False)
+    return float(out.value)
+
+
+def nys_test_matrix(seed: int, n: int, r: int, device="cuda:0"):
+    """Omega (n x r float64) drawn on the device from the seed (counter-based)."""
+    Om = torch.empty((n, r), dtype=torch.float64, device=device)
+    _check(load().nys_test_matrix(int(seed) & 0xFFFFFFFFFFFFFFFF, n, r, Om.data_ptr(), _stream()),
+           allow_not_converged=False)
+    return Om
+
+
+def nys_sketch(X, Omega, kind: int, sigma: float, prec: int = FP64, seed: int = 0, r: int | None = None):
+    """(Y, Q) of the Nystrom sketch: Q the orthonormalised test matrix, Y = K Q.
+    Omega (n x r float64) is read only; with Omega None, r columns are drawn on the
+    device from `seed`."""
     lib = load()
     _need_cuda(X, torch.float64, "X")
-    _need_cuda(Omega, torch.float64, "Omega")
     n, d = X.shape
-    r = Omega.shape[1]
-    if Omega.shape[0] != n:
-        raise ValueError("Omega must have n rows")
+    if Omega is not None:
+        _need_cuda(Omega, torch.float64, "Omega")
+        if Omega.shape[0] != n or (r is not None and Omega.shape[1] != r):
+            raise ValueError("Omega must be n x r")
+        r = Omega.shape[1]
+    elif r is None:
+        raise ValueError("r is required when Omega is None")
     Y = torch.empty((n, r), dtype=torch.float64, device=X.device)
+    Q = torch.empty((n, r), dtype=torch.float64, device=X.device)
     ws = _workspace(nys_workspace_bytes(OP_SKETCH, n, 0, d, r, 0, prec), X.device)
-    rc = lib.nys_sketch(NysKernel(kind, 0, float(sigma)), int(prec), X.data_ptr(), n, d, Omega.data_ptr(), r,
-                        Y.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    rc = lib.nys_sketch(NysKernel(kind, 0, float(sigma)), int(prec), X.data_ptr(), n, d,
+                        Omega.data_ptr() if Omega is not None else None, int(seed) & 0xFFFFFFFFFFFFFFFF, r,
+                        Q.data_ptr(), Y.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
     _check(rc, allow_not_converged=False)
-    return Y
+    return Y, Q
 
 
 def nys_precond_build(Y, Q, sketch_prec: int = FP64, with_fp32: bool = True) -> Preconditioner:
@@ -248,6 +303,36 @@ def nys_precond_build(Y, Q, sketch_prec: int = FP64, with_fp32: bool = True) -> 
     P.rank = int(cs.rank)
     P.nu = float(cs.nu)
     return P
+
+
+def nys_precond_adaptive(X, kind: int, sigma: float, rank_init: int, rank_max: int | None = None,
+                         num_power_iters: int = 10, error_tolerance: float = 1e-2, damping: str = "adaptive",
+                         prec: int = FP64, seed: int = 0, with_fp32: bool = True):
+    """Nystrom preconditioner with rank adaptation and damping mode (NystromConfig of the
+    paper's table tab:rlaopt-nystrom-config).  Returns (Preconditioner, error estimate);
+    the preconditioner's r is the rank the adaptation settled on."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    n, d = X.shape
+    rmax = rank_init if rank_max is None else int(rank_max)
+    mode = {"adaptive": DAMPING_ADAPTIVE, "non_adaptive": DAMPING_NON_ADAPTIVE}[damping]
+    cfg = NysNystromConfig(int(rank_init), rmax, int(num_power_iters), mode, float(error_tolerance),
+                           int(seed) & 0xFFFFFFFFFFFFFFFF)
+    U = torch.empty((n, rmax), dtype=torch.float64, device=X.device)
+    U32 = torch.empty((n, rmax), dtype=torch.float32, device=X.device) if with_fp32 else None
+    lam = torch.empty(rmax, dtype=torch.float64, device=X.device)
+    cs = NysPrecondC(n, rmax, 0, U.data_ptr(), U32.data_ptr() if U32 is not None else None, lam.data_ptr(), 0.0, 0.0)
+    ws = _workspace(nys_workspace_bytes(OP_PRECOND_ADAPTIVE, n, 0, d, rmax, 0, prec), X.device)
+    err = c_f64(0.0)
+    rc = lib.nys_precond_adaptive(NysKernel(kind, 0, float(sigma)), int(prec), X.data_ptr(), n, d, ctypes.byref(cfg),
+                                  ctypes.byref(cs), ctypes.byref(err), ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, allow_not_converged=False)
+    r = int(cs.r)
+    # U was written as n x r (row stride r) at the start of the buffer
+    Ur = U.reshape(-1)[: n * r].view(n, r)
+    U32r = U32.reshape(-1)[: n * r].view(n, r) if U32 is not None else None
+    P = Preconditioner(Ur, U32r, lam[:r], int(cs.rank), float(cs.nu), float(cs.shift))
+    return P, float(err.value)
 
 
 def nys_precond_apply(P: Preconditioner, lambdas, R, prec: int = FP64):
@@ -339,11 +424,13 @@ def nyspcg_backward(X, lam: float, xsol, gx, kind: int, sigma: float, P: Precond
     return adj, float(dl.value), float(ds.value), _info_list(info, 1)[0]
 
 
-def build_preconditioner(X, Omega, kind: int, sigma: float, sketch_prec: int = FP64, with_fp32: bool = True):
-    """Sketch then build: returns the preconditioner (Omega is overwritten by its orthonormalisation)."""
-    Y = nys_sketch(X, Omega, kind, sigma, sketch_prec)
-    P = nys_precond_build(Y, Omega, sketch_prec, with_fp32)
-    del Y
+def build_preconditioner(X, Omega, kind: int, sigma: float, sketch_prec: int = FP64, with_fp32: bool = True,
+                         r: int | None = None, seed: int = 0):
+    """Sketch then build: the Nystrom preconditioner for the test matrix Omega (read
+    only), or, with Omega None, for r columns drawn on the device from `seed`."""
+    Y, Q = nys_sketch(X, Omega, kind, sigma, sketch_prec, seed=seed, r=r)
+    P = nys_precond_build(Y, Q, sketch_prec, with_fp32)
+    del Y, Q
     return P
 
 
@@ -384,6 +471,19 @@ def nys_plan_chunks(prec: int, n: int, d: int, m: int) -> tuple[int, int]:
     tm, tail = c_i32(0), c_i32(0)
     _check(load().nys_plan_chunks(prec, n, d, m, ctypes.byref(tm), ctypes.byref(tail)))
     return tm.value, tail.value
+
+
+PROBE_BF16_MFMA, PROBE_F16_MFMA, PROBE_F64_MFMA, PROBE_EXP2, PROBE_COPY = range(5)
+
+
+def nys_peak_probe(which: int, iters: int = 0, workspace: torch.Tensor | None = None,
+                   device="cuda:0") -> float:
+    """Sustained rate of one unit (flop/s, exp/s or copied bytes/s; see include/nys.h)."""
+    ws = workspace if workspace is not None else _workspace(8 << 20, device)
+    rate = c_f64(0.0)
+    _check(load().nys_peak_probe(int(which), int(iters), ctypes.byref(rate), ws.data_ptr(), ws.numel(), _stream()),
+           allow_not_converged=False)
+    return float(rate.value)
 
 
 def autotune(X, kind: int, sigma: float, prec: int, m_max: int, cache: str | None = None, reps: int = 1,

@@ -8,9 +8,10 @@ with a = (K + lambda I)^{-1} (dL/dx) (the adjoint solve, same preconditioner),
     dL/db = a,   dL/dlambda = -a^T x,   dL/dsigma = -a^T (dK/dsigma) x.
 
 Both the forward solve and the adjoint run in libnys (nyspcg_solve,
-nyspcg_backward); the kernel products use kernel_matvec, whose deriv=1 mode
-gives (dK/dsigma) v.  The preconditioner is held fixed (stop-gradient): the
-converged solution does not depend on it.
+nyspcg_backward); the kernel products use kernel_matvec, and the explicit
+sigma-term g^T (dK/dsigma) v of a product is one kernel_dot call.  The
+preconditioner is held fixed (stop-gradient): the converged solution does not
+depend on it.
 """
 from __future__ import annotations
 
@@ -44,8 +45,8 @@ class KernelProduct(torch.autograd.Function):
         if ctx.needs_input_grad[2]:
             gv = nys.kernel_matvec(Xc, Xr, g, ctx.kind, ctx.sigma, nys.FP64)
         if ctx.sigma_is_tensor and ctx.needs_input_grad[3]:
-            dk_v = nys.kernel_matvec(Xr, Xc, v.contiguous(), ctx.kind, ctx.sigma, nys.FP64, deriv=1)
-            gs = torch.dot(g.reshape(-1), dk_v.reshape(-1)).reshape(())
+            gs = torch.tensor(nys.kernel_dot(Xr, Xc, g, v.contiguous(), ctx.kind, ctx.sigma, deriv=1),
+                              dtype=torch.float64, device=g.device)
         return None, None, gv, gs, None
 
 

@@ -17,18 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnys.so")
 
-SOURCES = [
-    "api.hip",
-    "kmv_host.hip",
-    "kmv_f64.hip",
-    "kmv_f32.hip",
-    "kmv_bf16.hip",
-    "kmv_f16.hip",
-    "kmv_f64p.hip",
-    "blas.hip",
-    "small.hip",
-    "pcg.hip",
-]
+# every HIP source of csrc/ is one translation unit of the library
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

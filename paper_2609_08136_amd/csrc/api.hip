@@ -58,6 +58,7 @@ int32_t check_ws(const Arena &a) {
 // ------------------------------------------------------------ kernel product buffers
 struct KmvBufs {
   double *mu = nullptr, *mpart = nullptr;
+  int *bad = nullptr;   // set by the packing when a point is not finite
   Packed rows, cols;
   void *partial = nullptr, *vhi = nullptr, *vlo = nullptr;
 };
@@ -75,6 +76,7 @@ void plan_points(Packed &p, int64_t n, int d, int prec, Arena &ws) {
 void plan_kmv(KmvBufs &b, int64_t nr, int64_t nc, int d, int m_lo, int m_max, int prec, Arena &ws) {
   b.mu = ws.take<double>(d);
   b.mpart = ws.take<double>(col_mean_partial_elems(nc, d));
+  b.bad = ws.take<int>(4);
   plan_points(b.rows, nr, d, prec, ws);
   plan_points(b.cols, nc, d, prec, ws);
   size_t pb = 0, ve = 0, vl = 0, a = 0, e = 0, l = 0;
@@ -95,11 +97,22 @@ void plan_kmv(KmvBufs &b, int64_t nr, int64_t nc, int d, int m_lo, int m_max, in
   b.vlo = vl ? ws.take<bf16bits>(vl) : nullptr;
 }
 
+// Centre and pack both point sets.  Synchronises the stream once to read the
+// packing's finiteness flag: a NaN or Inf coordinate returns NYS_ENUMERIC (a NaN
+// would otherwise turn every packed point, through the column mean, into NaN).
 int32_t prep_points(KmvBufs &b, const nys_kernel &k, int prec, const double *Xr, const double *Xc,
                     int d, hipStream_t s) {
+  NYS_CHECK_HIP(hipMemsetAsync(b.bad, 0, sizeof(int), s));
   NYS_RETURN_IF(launch_col_mean(Xc, b.cols.n, d, b.mu, b.mpart, s));
-  NYS_RETURN_IF(launch_pack(Xr, b.rows.n, d, b.mu, k, prec, SIDE_ROW, &b.rows, s));
-  NYS_RETURN_IF(launch_pack(Xc, b.cols.n, d, b.mu, k, prec, SIDE_COL, &b.cols, s));
+  NYS_RETURN_IF(launch_pack(Xr, b.rows.n, d, b.mu, k, prec, SIDE_ROW, &b.rows, b.bad, s));
+  NYS_RETURN_IF(launch_pack(Xc, b.cols.n, d, b.mu, k, prec, SIDE_COL, &b.cols, b.bad, s));
+  int bad = 0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&bad, b.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (bad) {
+    set_error("NaN or Inf in the point coordinates X");
+    return NYS_ENUMERIC;
+  }
   return NYS_OK;
 }
 
@@ -160,6 +173,7 @@ int32_t plan_autotune(AutotunePlan &p, int64_t n_rows, int64_t n, int d, int m, 
   // points packed once; scratch for the largest candidate (the table is restored after)
   p.kv.mu = ws.take<double>(d);
   p.kv.mpart = ws.take<double>(col_mean_partial_elems(n, d));
+  p.kv.bad = ws.take<int>(4);
   plan_points(p.kv.rows, n_rows, d, prec, ws);
   plan_points(p.kv.cols, n, d, prec, ws);
   size_t pb = 0, ve = 0, vl = 0, a = 0, e = 0, l = 0;
@@ -294,6 +308,18 @@ void plan_solve(SolvePlan &p, int64_t n, int d, int r, int m, int prec, bool ref
   }
 }
 
+// kernel_dot: the product K v into tmp, then one ordered dot product with u
+struct DotPlan {
+  KmvBufs kv;
+  double *tmp = nullptr, *red = nullptr, *out = nullptr;
+};
+void plan_dot(DotPlan &p, int64_t nr, int64_t nc, int d, Arena &ws) {
+  plan_kmv(p.kv, nr, nc, d, 1, 1, NYS_FP64, ws);
+  p.tmp = ws.take<double>((size_t)nr);
+  p.red = ws.take<double>((size_t)colred_shape(nr, 1).nb);
+  p.out = ws.take<double>(2);
+}
+
 struct DerivPlan {
   KmvBufs kv;
   double *tmp = nullptr, *red = nullptr, *out = nullptr;
@@ -321,6 +347,216 @@ int32_t apply_precond_or_copy(const nys_precond *P, SolvePlan &sp, const T *R, i
 // The PCG driver (solve_columns).
 #include "solve_impl.h"
 
+// The stabilised approximation from a sketch (Y, Q of r columns): fills P->U (n x r),
+// P->lam_hat, P->U32 (when given), P->rank and P->nu.
+int32_t build_impl(const double *Y, const double *Q, int64_t n, int r, int sketch_prec, nys_precond *P,
+                   BuildPlan &p, hipStream_t s) {
+  const int64_t cnt = n * (int64_t)r;
+  NYS_RETURN_IF(launch_sumsq(Y, cnt, p.ssq_part, p.ssq, s));
+  double ssq = 0.0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&ssq, p.ssq, sizeof(double), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (!std::isfinite(ssq)) {
+    set_error("nys_precond_build: NaN or Inf in the sketch");
+    return NYS_ENUMERIC;
+  }
+  const double yf = std::sqrt(ssq);
+  const double cprec = sketch_prec == NYS_FP64 ? 0.0 : (sketch_prec == NYS_FP32 ? std::ldexp(1.0, -21) : std::ldexp(1.0, -14));
+  double nu = std::max(std::sqrt((double)n) * std::ldexp(1.0, -52) * yf, cprec * yf / std::sqrt((double)r));
+  if (!(nu > 0.0)) nu = std::ldexp(1.0, -52);
+  const int splits = gemm_tn_splits(n, r, r);
+  bool ok = false;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    NYS_CHECK_HIP(hipMemcpyAsync(p.Ynu, Y, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+    NYS_RETURN_IF(launch_axpy(nu, Q, p.Ynu, cnt, s));
+    NYS_RETURN_IF(gemm_tn<double>(Q, r, p.Ynu, r, n, r, r, p.M, r, p.Mpart, splits, s));
+    NYS_RETURN_IF(launch_symmetrise(p.M, p.L, r, s));
+    NYS_RETURN_IF(launch_chol(p.L, r, p.flag, s));
+    int flag = 0;
+    NYS_CHECK_HIP(hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    if (flag == 0) {
+      ok = true;
+      break;
+    }
+    nu *= 10.0;
+  }
+  if (!ok) {
+    set_error("nys_precond_build: shifted Cholesky of the sketch core failed after 5 retries");
+    return NYS_ENOTPD;
+  }
+  // B = Y_nu L^{-T};  B^T B = V S^2 V^T;  U = B V S^{-1}
+  NYS_RETURN_IF(launch_trinv_lower(p.L, p.Linv, r, s));
+  NYS_RETURN_IF(launch_transpose(p.Linv, p.LinvT, r, s));
+  NYS_RETURN_IF(gemm_nn<double>(p.Ynu, r, p.LinvT, r, n, r, r, p.Bm, r, 0, nullptr, 0, nullptr, s));
+  NYS_RETURN_IF(gemm_tn<double>(p.Bm, r, p.Bm, r, n, r, r, p.G, r, p.Mpart, splits, s));
+  NYS_RETURN_IF(launch_symmetrise(p.G, p.Gs, r, s));
+  NYS_RETURN_IF(jacobi_eig(p.Gs, p.Gbuf, p.Vev, p.w, r, p.jac, s));
+  NYS_RETURN_IF(launch_eig_finish(p.w, p.Vev, r, nu, p.T, P->lam_hat, p.rank, s));
+  NYS_RETURN_IF(gemm_nn<double>(p.Bm, r, p.T, r, n, r, r, P->U, r, 0, nullptr, 0, nullptr, s));
+  if (P->U32) NYS_RETURN_IF(launch_copy_d2f(P->U, P->U32, cnt, s));
+  int rank = 0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&rank, p.rank, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  P->rank = rank;
+  P->nu = nu;
+  return NYS_OK;
+}
+
+// ------------------------------------------------------------ rank adaptation
+// Scratch of nys_precond_adaptive: the test matrix and K times it (n x rank_max), the
+// orthonormalised sketch of the current rank, the Cholesky QR factors, the build, and
+// the vectors of the power iteration.
+struct AdaptPlan {
+  double *Om = nullptr, *Yraw = nullptr, *Q = nullptr, *Y = nullptr;
+  float *O32 = nullptr, *Y32 = nullptr, *v32 = nullptr, *w32 = nullptr;
+  double *G = nullptr, *Gpart = nullptr, *Linv = nullptr, *LinvT = nullptr;
+  double *v = nullptr, *w = nullptr, *t = nullptr, *c = nullptr, *cpart = nullptr, *red = nullptr, *out = nullptr;
+  int *flag = nullptr;
+  KmvBufs kv;
+  BuildPlan bp;
+};
+void plan_adapt(AdaptPlan &p, int64_t n, int d, int rmax, int prec, Arena &ws) {
+  const size_t cnt = (size_t)n * rmax;
+  p.Om = ws.take<double>(cnt);
+  p.Yraw = ws.take<double>(cnt);
+  p.Q = ws.take<double>(cnt);
+  p.Y = ws.take<double>(cnt);
+  if (prec != NYS_FP64) {
+    p.O32 = ws.take<float>(cnt);
+    p.Y32 = ws.take<float>(cnt);
+    p.v32 = ws.take<float>((size_t)n);
+    p.w32 = ws.take<float>((size_t)n);
+  }
+  const int splits = gemm_tn_splits(n, rmax, rmax);
+  p.G = ws.take<double>((size_t)rmax * rmax);
+  p.Gpart = ws.take<double>((size_t)splits * rmax * rmax);
+  p.Linv = ws.take<double>((size_t)rmax * rmax);
+  p.LinvT = ws.take<double>((size_t)rmax * rmax);
+  p.flag = ws.take<int>(4);
+  p.v = ws.take<double>((size_t)n);
+  p.w = ws.take<double>((size_t)n);
+  p.t = ws.take<double>((size_t)n);
+  p.c = ws.take<double>((size_t)rmax);
+  p.cpart = ws.take<double>((size_t)gemm_tn_splits(n, rmax, 1) * rmax);
+  p.red = ws.take<double>((size_t)colred_shape(n, 1).nb);
+  p.out = ws.take<double>(2);
+  plan_kmv(p.kv, n, n, d, 1, rmax, prec, ws);
+  plan_build(p.bp, n, rmax, ws);
+}
+
+__global__ void scale_vec_kernel(const double *x, const double *coef, double *y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = coef[i] * x[i];
+}
+__global__ void scale_by_kernel(double *y, double a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] *= a;
+}
+
+// host value of a . b (float64 vectors of n)
+int32_t dot_host(const double *a, const double *b, int64_t n, double *red, double *out, double *h, hipStream_t s) {
+  NYS_RETURN_IF(colred<double>(0, a, const_cast<double *>(b), nullptr, nullptr, n, 1, nullptr, red, s));
+  NYS_RETURN_IF(colfinal(red, n, 1, 0, out, nullptr, nullptr, nullptr, nullptr, s));
+  NYS_CHECK_HIP(hipMemcpyAsync(h, out, sizeof(double), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  return NYS_OK;
+}
+
+// Rank doubling: K is applied only to the test-matrix columns added since the last
+// round (Yraw = K Omega), the first l columns are orthonormalised by Cholesky QR
+// (Q = Omega_l L^-T, Y = Yraw_l L^-T: the same sketch as K Q), the approximation is
+// built, and its error |K - K_hat|_2 is estimated by power iterations.
+int32_t adaptive_impl(const nys_kernel &k, int prec, const double *X, int64_t n, int d, const nys_nystrom_config &cfg,
+                      int rmax, nys_precond *P, double *err_out, AdaptPlan &p, hipStream_t s) {
+  const int64_t cnt = n * (int64_t)rmax;
+  NYS_RETURN_IF(launch_gaussian(cfg.seed, cnt, p.Om, s));
+  if (prec != NYS_FP64) NYS_RETURN_IF(launch_copy_d2f(p.Om, p.O32, cnt, s));
+  NYS_RETURN_IF(prep_points(p.kv, k, prec, X, X, d, s));
+  int l = std::min(cfg.rank_init, rmax), done_cols = 0;
+  double err = 0.0;
+  const unsigned gb = (unsigned)ceil_div(n, 256);
+  while (true) {
+    // K times the new columns
+    if (prec == NYS_FP64) {
+      NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, p.Om + done_cols, l - done_cols, rmax, p.Yraw + done_cols, rmax,
+                            1.0, 0.0, s));
+    } else {
+      NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, p.O32 + done_cols, l - done_cols, rmax, p.Y32 + done_cols, rmax,
+                            1.0, 0.0, s));
+      NYS_RETURN_IF(launch_copy_f2d(p.Y32, p.Yraw, cnt, s));
+    }
+    done_cols = l;
+    // Cholesky QR of the first l columns
+    const int splits = gemm_tn_splits(n, l, l);
+    NYS_RETURN_IF(gemm_tn<double>(p.Om, rmax, p.Om, rmax, n, l, l, p.G, l, p.Gpart, splits, s));
+    NYS_RETURN_IF(launch_chol(p.G, l, p.flag, s));
+    int flag = 0;
+    NYS_CHECK_HIP(hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    if (flag) {
+      set_error("nys_precond_adaptive: the test matrix is rank deficient");
+      return NYS_ENOTPD;
+    }
+    NYS_RETURN_IF(launch_trinv_lower(p.G, p.Linv, l, s));
+    NYS_RETURN_IF(launch_transpose(p.Linv, p.LinvT, l, s));
+    NYS_RETURN_IF(gemm_nn<double>(p.Om, rmax, p.LinvT, l, n, l, l, p.Q, l, 0, nullptr, 0, nullptr, s));
+    NYS_RETURN_IF(gemm_nn<double>(p.Yraw, rmax, p.LinvT, l, n, l, l, p.Y, l, 0, nullptr, 0, nullptr, s));
+    nys_precond Pl = *P;
+    Pl.r = l;
+    NYS_RETURN_IF(build_impl(p.Y, p.Q, n, l, prec, &Pl, p.bp, s));
+    P->rank = Pl.rank;
+    P->nu = Pl.nu;
+    P->r = l;
+    // power iteration on E = K - U diag(lam_hat) U^T from a seeded start vector
+    err = 0.0;
+    if (cfg.num_power_iters > 0) {
+      double h = 0.0;
+      NYS_RETURN_IF(launch_gaussian(cfg.seed + 1, n, p.v, s));
+      NYS_RETURN_IF(dot_host(p.v, p.v, n, p.red, p.out, &h, s));
+      hipLaunchKernelGGL(scale_by_kernel, dim3(gb), dim3(256), 0, s, p.v, 1.0 / std::sqrt(h), n);
+      NYS_LAUNCH_CHECK();
+      for (int it = 0; it < cfg.num_power_iters; ++it) {
+        if (prec == NYS_FP64) {
+          NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, p.v, 1, 1, p.w, 1, 1.0, 0.0, s));
+        } else {
+          NYS_RETURN_IF(launch_copy_d2f(p.v, p.v32, n, s));
+          NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, p.v32, 1, 1, p.w32, 1, 1.0, 0.0, s));
+          NYS_RETURN_IF(launch_copy_f2d(p.w32, p.w, n, s));
+        }
+        const int cs = gemm_tn_splits(n, l, 1);
+        NYS_RETURN_IF(gemm_tn<double>(P->U, l, p.v, 1, n, l, 1, p.c, 1, p.cpart, cs, s));
+        hipLaunchKernelGGL(scale_vec_kernel, dim3((unsigned)ceil_div(l, 256)), dim3(256), 0, s, p.c, P->lam_hat,
+                           p.c, (int64_t)l);
+        NYS_LAUNCH_CHECK();
+        NYS_RETURN_IF(gemm_nn<double>(P->U, l, p.c, 1, n, l, 1, p.t, 1, 0, nullptr, 0, nullptr, s));
+        NYS_RETURN_IF(launch_axpy(-1.0, p.t, p.w, n, s));           // w = E v
+        NYS_RETURN_IF(dot_host(p.v, p.w, n, p.red, p.out, &err, s));   // Rayleigh quotient
+        NYS_RETURN_IF(dot_host(p.w, p.w, n, p.red, p.out, &h, s));
+        if (!(h > 0.0) || !std::isfinite(h)) break;
+        NYS_CHECK_HIP(hipMemcpyAsync(p.v, p.w, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(scale_by_kernel, dim3(gb), dim3(256), 0, s, p.v, 1.0 / std::sqrt(h), n);
+        NYS_LAUNCH_CHECK();
+      }
+    }
+    double lam1 = 0.0;
+    NYS_CHECK_HIP(hipMemcpyAsync(&lam1, P->lam_hat, sizeof(double), hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    if (err <= cfg.error_tolerance * lam1 || l >= rmax) break;
+    l = std::min(2 * l, rmax);
+  }
+  // the build wrote U as n x l (row stride l) at the start of the n x rank_max buffer;
+  // zero the unused tail of lam_hat so that the buffers describe exactly the result
+  if (P->r < rmax) NYS_RETURN_IF(launch_fill(P->lam_hat + P->r, 0.0, rmax - P->r, s));
+  P->shift = 0.0;
+  if (cfg.damping_mode == NYS_DAMPING_ADAPTIVE && P->rank > 0) {
+    NYS_CHECK_HIP(hipMemcpyAsync(&P->shift, P->lam_hat + (P->rank - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (err_out) *err_out = err;
+  return NYS_OK;
+}
+
 int32_t check_precond(const nys_precond *P, int64_t n, int prec) {
   if (!P) return NYS_OK;
   if (P->n != n) return einval("preconditioner built for a different n");
@@ -344,6 +580,10 @@ int32_t check_opts(const nys_pcg_opts *o) {
 extern "C" {
 
 const char *nys_last_error(void) { return last_error_cstr(); }
+
+int32_t nys_peak_probe(int32_t which, int32_t iters, double *rate, void *ws, size_t ws_bytes, void *stream) {
+  return peak_probe(which, iters, rate, ws, ws_bytes, as_stream(stream));
+}
 const char *nys_version(void) { return "libnys 0.1.0 (gfx950)"; }
 
 int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_t r, int32_t m,
@@ -381,6 +621,16 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
       plan_solve(p, std::max<int64_t>(n, 1), std::max(d, 1), r, 1, prec, true, true, a);
       DerivPlan q;
       plan_deriv(q, std::max<int64_t>(n, 1), std::max(d, 1), a);
+      break;
+    }
+    case NYS_OP_PRECOND_ADAPTIVE: {
+      AdaptPlan p;
+      plan_adapt(p, std::max<int64_t>(n, 1), std::max(d, 1), std::max(r, 1), prec, a);
+      break;
+    }
+    case NYS_OP_KERNEL_DOT: {
+      DotPlan p;
+      plan_dot(p, std::max<int64_t>(n, 1), std::max<int64_t>(n2, 1), std::max(d, 1), a);
       break;
     }
     case NYS_OP_AUTOTUNE: {
@@ -504,13 +754,21 @@ int32_t kernel_matvec(nys_kernel k, int32_t deriv, int32_t prec, const double *X
   return run_kmv(p.kv, k, deriv, prec, same, V, m, m, Out, m, alpha, beta, s);
 }
 
-int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32_t d, double *Omega,
-                   int32_t r, double *Y, void *ws, size_t ws_bytes, void *stream) {
+int32_t nys_test_matrix(uint64_t seed, int64_t n, int32_t r, double *Omega, void *stream) {
+  if (n < 1 || r < 1) return einval("need n >= 1 and r >= 1");
+  if (!Omega) return einval("null pointer");
+  return launch_gaussian(seed, n * (int64_t)r, Omega, as_stream(stream));
+}
+
+int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32_t d, const double *Omega,
+                   uint64_t seed, int32_t r, double *Q, double *Y, void *ws, size_t ws_bytes, void *stream) {
   NYS_RETURN_IF(check_kernel(k));
   if (!valid_prec(prec)) return einval("unsupported precision");
   if (n < 1 || d < 1 || d > max_dim(prec)) return einval("n >= 1 and 1 <= d <= max required");
   if (r < 1 || r > n || r > 1024) return einval("need 1 <= r <= min(n, 1024)");
-  if (!X || !Omega || !Y || !ws) return einval("null pointer");
+  if (!X || !Q || !Y || !ws) return einval("null pointer");
+  const int64_t cnt = n * (int64_t)r;
+  if (Omega && Omega + cnt > Q && Q + cnt > Omega) return einval("Q must not overlap Omega");
   hipStream_t s = as_stream(stream);
   Arena a;
   a.base = reinterpret_cast<char *>(ws);
@@ -518,9 +776,15 @@ int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32
   SketchPlan p;
   plan_sketch(p, n, d, r, prec, a);
   NYS_RETURN_IF(check_ws(a));
+  // the test matrix: the caller's, or drawn from the seed into Qtmp
+  const double *Om = Omega;
+  if (!Om) {
+    NYS_RETURN_IF(launch_gaussian(seed, cnt, p.Qtmp, s));
+    Om = p.Qtmp;
+  }
   // Q = Omega L^{-T} with L L^T = Omega^T Omega (Cholesky QR)
   const int splits = gemm_tn_splits(n, r, r);
-  NYS_RETURN_IF(gemm_tn<double>(Omega, r, Omega, r, n, r, r, p.G, r, p.Gpart, splits, s));
+  NYS_RETURN_IF(gemm_tn<double>(Om, r, Om, r, n, r, r, p.G, r, p.Gpart, splits, s));
   NYS_RETURN_IF(launch_chol(p.G, r, p.flag, s));
   int flag = 0;
   NYS_CHECK_HIP(hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -531,17 +795,41 @@ int32_t nys_sketch(nys_kernel k, int32_t prec, const double *X, int64_t n, int32
   }
   NYS_RETURN_IF(launch_trinv_lower(p.G, p.Linv, r, s));
   NYS_RETURN_IF(launch_transpose(p.Linv, p.LinvT, r, s));
-  NYS_RETURN_IF(gemm_nn<double>(Omega, r, p.LinvT, r, n, r, r, p.Qtmp, r, 0, nullptr, 0, nullptr, s));
-  NYS_CHECK_HIP(hipMemcpyAsync(Omega, p.Qtmp, sizeof(double) * n * r, hipMemcpyDeviceToDevice, s));
+  NYS_RETURN_IF(gemm_nn<double>(Om, r, p.LinvT, r, n, r, r, Q, r, 0, nullptr, 0, nullptr, s));
   // Y = K Q
   NYS_RETURN_IF(prep_points(p.kv, k, prec, X, X, d, s));
   if (prec == NYS_FP64) {
-    NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, Omega, r, r, Y, r, 1.0, 0.0, s));
+    NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, Q, r, r, Y, r, 1.0, 0.0, s));
   } else {
-    NYS_RETURN_IF(launch_copy_d2f(Omega, p.Q32, n * (int64_t)r, s));
+    NYS_RETURN_IF(launch_copy_d2f(Q, p.Q32, cnt, s));
     NYS_RETURN_IF(run_kmv(p.kv, k, 0, prec, 1, p.Q32, r, r, p.Y32, r, 1.0, 0.0, s));
-    NYS_RETURN_IF(launch_copy_f2d(p.Y32, Y, n * (int64_t)r, s));
+    NYS_RETURN_IF(launch_copy_f2d(p.Y32, Y, cnt, s));
   }
+  return NYS_OK;
+}
+
+int32_t kernel_dot(nys_kernel k, int32_t deriv, const double *Xr, int64_t nr, const double *Xc, int64_t nc,
+                   int32_t d, const double *u, const double *v, double *out, void *ws, size_t ws_bytes,
+                   void *stream) {
+  NYS_RETURN_IF(check_kernel(k));
+  if (deriv != 0 && deriv != 1) return einval("deriv must be 0 or 1");
+  if (nr < 1 || nc < 1) return einval("need nr >= 1 and nc >= 1");
+  if (d < 1 || d > max_dim(NYS_FP64)) return einval("d out of range");
+  if (!Xr || !Xc || !u || !v || !out || !ws) return einval("null pointer");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  DotPlan p;
+  plan_dot(p, nr, nc, d, a);
+  NYS_RETURN_IF(check_ws(a));
+  const int same = (Xr == Xc && nr == nc) ? 1 : 0;
+  NYS_RETURN_IF(prep_points(p.kv, k, NYS_FP64, Xr, Xc, d, s));
+  NYS_RETURN_IF(run_kmv(p.kv, k, deriv, NYS_FP64, same, v, 1, 1, p.tmp, 1, 1.0, 0.0, s));
+  NYS_RETURN_IF(colred<double>(0, u, p.tmp, nullptr, nullptr, nr, 1, nullptr, p.red, s));
+  NYS_RETURN_IF(colfinal(p.red, nr, 1, 0, p.out, nullptr, nullptr, nullptr, nullptr, s));
+  NYS_CHECK_HIP(hipMemcpyAsync(out, p.out, sizeof(double), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
   return NYS_OK;
 }
 
@@ -558,56 +846,35 @@ int32_t nys_precond_build(const double *Y, const double *Q, int64_t n, int32_t r
   BuildPlan p;
   plan_build(p, n, r, a);
   NYS_RETURN_IF(check_ws(a));
-  const int64_t cnt = n * (int64_t)r;
-  NYS_RETURN_IF(launch_sumsq(Y, cnt, p.ssq_part, p.ssq, s));
-  double ssq = 0.0;
-  NYS_CHECK_HIP(hipMemcpyAsync(&ssq, p.ssq, sizeof(double), hipMemcpyDeviceToHost, s));
-  NYS_CHECK_HIP(hipStreamSynchronize(s));
-  if (!std::isfinite(ssq)) {
-    set_error("nys_precond_build: NaN or Inf in the sketch");
-    return NYS_ENUMERIC;
-  }
-  const double yf = std::sqrt(ssq);
-  const double cprec = sketch_prec == NYS_FP64 ? 0.0 : (sketch_prec == NYS_FP32 ? std::ldexp(1.0, -21) : std::ldexp(1.0, -14));
-  double nu = std::max(std::sqrt((double)n) * std::ldexp(1.0, -52) * yf, cprec * yf / std::sqrt((double)r));
-  if (!(nu > 0.0)) nu = std::ldexp(1.0, -52);
-  const int splits = gemm_tn_splits(n, r, r);
-  bool ok = false;
-  for (int attempt = 0; attempt < 6; ++attempt) {
-    NYS_CHECK_HIP(hipMemcpyAsync(p.Ynu, Y, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
-    NYS_RETURN_IF(launch_axpy(nu, Q, p.Ynu, cnt, s));
-    NYS_RETURN_IF(gemm_tn<double>(Q, r, p.Ynu, r, n, r, r, p.M, r, p.Mpart, splits, s));
-    NYS_RETURN_IF(launch_symmetrise(p.M, p.L, r, s));
-    NYS_RETURN_IF(launch_chol(p.L, r, p.flag, s));
-    int flag = 0;
-    NYS_CHECK_HIP(hipMemcpyAsync(&flag, p.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    NYS_CHECK_HIP(hipStreamSynchronize(s));
-    if (flag == 0) {
-      ok = true;
-      break;
-    }
-    nu *= 10.0;
-  }
-  if (!ok) {
-    set_error("nys_precond_build: shifted Cholesky of the sketch core failed after 5 retries");
-    return NYS_ENOTPD;
-  }
-  // B = Y_nu L^{-T};  B^T B = V S^2 V^T;  U = B V S^{-1}
-  NYS_RETURN_IF(launch_trinv_lower(p.L, p.Linv, r, s));
-  NYS_RETURN_IF(launch_transpose(p.Linv, p.LinvT, r, s));
-  NYS_RETURN_IF(gemm_nn<double>(p.Ynu, r, p.LinvT, r, n, r, r, p.Bm, r, 0, nullptr, 0, nullptr, s));
-  NYS_RETURN_IF(gemm_tn<double>(p.Bm, r, p.Bm, r, n, r, r, p.G, r, p.Mpart, splits, s));
-  NYS_RETURN_IF(launch_symmetrise(p.G, p.Gs, r, s));
-  NYS_RETURN_IF(jacobi_eig(p.Gs, p.Gbuf, p.Vev, p.w, r, p.jac, s));
-  NYS_RETURN_IF(launch_eig_finish(p.w, p.Vev, r, nu, p.T, P->lam_hat, p.rank, s));
-  NYS_RETURN_IF(gemm_nn<double>(p.Bm, r, p.T, r, n, r, r, P->U, r, 0, nullptr, 0, nullptr, s));
-  if (P->U32) NYS_RETURN_IF(launch_copy_d2f(P->U, P->U32, cnt, s));
-  int rank = 0;
-  NYS_CHECK_HIP(hipMemcpyAsync(&rank, p.rank, sizeof(int), hipMemcpyDeviceToHost, s));
-  NYS_CHECK_HIP(hipStreamSynchronize(s));
-  P->rank = rank;
-  P->nu = nu;
-  return NYS_OK;
+  P->shift = 0.0;
+  return build_impl(Y, Q, n, r, sketch_prec, P, p, s);
+}
+
+int32_t nys_precond_adaptive(nys_kernel k, int32_t prec, const double *X, int64_t n, int32_t d,
+                             const nys_nystrom_config *cfg, nys_precond *P, double *err_out, void *ws,
+                             size_t ws_bytes, void *stream) {
+  NYS_RETURN_IF(check_kernel(k));
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (n < 1 || d < 1 || d > max_dim(prec)) return einval("n >= 1 and 1 <= d <= max required");
+  if (!X || !cfg || !P || !ws) return einval("null pointer");
+  const int rmax = cfg->rank_max > 0 ? cfg->rank_max : cfg->rank_init;
+  if (cfg->rank_init < 1 || rmax < cfg->rank_init || rmax > n || rmax > 1024)
+    return einval("need 1 <= rank_init <= rank_max <= min(n, 1024)");
+  if (cfg->num_power_iters < 0) return einval("num_power_iters must be >= 0");
+  if (!(cfg->error_tolerance >= 0.0) || !std::isfinite(cfg->error_tolerance))
+    return einval("error_tolerance must be finite and >= 0");
+  if (cfg->damping_mode != NYS_DAMPING_NON_ADAPTIVE && cfg->damping_mode != NYS_DAMPING_ADAPTIVE)
+    return einval("unknown damping mode");
+  if (P->n != n || P->r != rmax || !P->U || !P->lam_hat)
+    return einval("preconditioner buffers must be sized n x rank_max");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  AdaptPlan p;
+  plan_adapt(p, n, d, rmax, prec, a);
+  NYS_RETURN_IF(check_ws(a));
+  return adaptive_impl(k, prec, X, n, d, *cfg, rmax, P, err_out, p, s);
 }
 
 int32_t nys_precond_apply(const nys_precond *P, const double *lambdas, int32_t prec, const void *R,

@@ -165,7 +165,7 @@ __device__ inline void exp_tab_init(double *tab, int tid) {
   if (tid < 64) tab[tid] = exp2((double)tid * (1.0 / 64.0));
 }
 __device__ inline double exp_neg_tab(double t, const double *tab) {
-  t = fmax(t, -1100.0);
+  t = t < -1100.0 ? -1100.0 : t;                               // a NaN argument stays NaN
   const double kd = rint(t * 0x1.71547652b82fep+6);           // 64 / ln 2
   const int k = (int)kd;
   double r = fma(-kd, 0x1.62e42fefa0000p-7, t);                // head of ln2/64
@@ -187,7 +187,7 @@ __device__ inline double kernel_value_tab(double t, double cL, double dcoef, con
     if constexpr (DERIV) k *= (-t) * dcoef;
     return k;
   } else {
-    const double dist = sqrt(t < 0.0 ? -t : 0.0);
+    const double dist = sqrt(t > 0.0 ? 0.0 : -t);              // NaN stays NaN
     double k = exp_neg_tab(-cL * dist, tab);
     if constexpr (DERIV) k *= dist * dcoef;
     return k;

@@ -117,17 +117,21 @@ template <> struct SplitTerms<10> {
 // row side: [x | 1 | -kappa |x|^2], so that the dot product of a row point and a
 // column point is the exponent kappa (2 x.y - |x|^2 - |y|^2) of the kernel.
 // Points are centred on the column mean mu first (distances do not change).
+// A point with a NaN or infinite coordinate (or a non-finite centre, from such a
+// point among the column points) sets *bad.
 template <int PREC, int SIDE, int NT = 3>
 __global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu, double kappa,
-                            void *out, int Kp, int64_t n_pad) {
+                            void *out, int Kp, int64_t n_pad, int *bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pad) return;
   double s = 0.0;
-  if (i < n)
+  if (i < n) {
     for (int l = 0; l < d; ++l) {
       double v = X[i * d + l] - mu[l];
       s += v * v;
     }
+    if (!isfinite(s)) *bad = 1;
+  }
   if constexpr (PREC == NYS_FP64 || PREC == NYS_FP32) {
     using E = typename Tr<PREC>::E;
     E *o = reinterpret_cast<E *>(out) + i * Kp;
@@ -173,25 +177,25 @@ __global__ void pack_kernel(const double *X, int64_t n, int d, const double *mu,
 }
 
 int32_t launch_pack(const double *X, int64_t n, int d, const double *mu, const nys_kernel &k,
-                    int prec, int side, Packed *out, hipStream_t s) {
+                    int prec, int side, Packed *out, int *bad, hipStream_t s) {
   prec = packing_prec(prec);
   const double kappa = kernel_kappa(k, prec);
   const int64_t n_pad = out->n_pad;
   dim3 grid((unsigned)ceil_div(n_pad, 128)), block(128);
-#define NYS_PACK(P, S) hipLaunchKernelGGL((pack_kernel<P, S>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad)
+#define NYS_PACK(P, S) hipLaunchKernelGGL((pack_kernel<P, S>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad, bad)
   if (prec == NYS_FP64) { if (side == SIDE_COL) NYS_PACK(NYS_FP64, SIDE_COL); else NYS_PACK(NYS_FP64, SIDE_ROW); }
   else if (prec == NYS_FP32) { if (side == SIDE_COL) NYS_PACK(NYS_FP32, SIDE_COL); else NYS_PACK(NYS_FP32, SIDE_ROW); }
   else if (prec == NYS_BF16X3) { if (side == SIDE_COL) NYS_PACK(NYS_BF16X3, SIDE_COL); else NYS_PACK(NYS_BF16X3, SIDE_ROW); }
   else if (prec == NYS_BF16X3_D6) {
     if (side == SIDE_COL)
-      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_COL, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_COL, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad, bad);
     else
-      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_ROW, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_ROW, 6>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad, bad);
   } else {
     if (side == SIDE_COL)
-      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_COL, 10>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_COL, 10>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad, bad);
     else
-      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_ROW, 10>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad);
+      hipLaunchKernelGGL((pack_kernel<NYS_BF16X3, SIDE_ROW, 10>), grid, block, 0, s, X, n, d, mu, kappa, out->data, out->Kp, n_pad, bad);
   }
 #undef NYS_PACK
   NYS_LAUNCH_CHECK();

@@ -106,8 +106,9 @@ int32_t launch_col_mean(const double *X, int64_t n, int d, double *mu, double *p
                         hipStream_t s);
 size_t col_mean_partial_elems(int64_t n, int d);
 
+// Packs the points; a non-finite coordinate (or centre) sets *bad (device int).
 int32_t launch_pack(const double *X, int64_t n, int d, const double *mu, const nys_kernel &k,
-                    int prec, int side, Packed *out, hipStream_t s);
+                    int prec, int side, Packed *out, int *bad, hipStream_t s);
 
 // ---------------------------------------------------------------- kernel product
 struct KmvPlan {
@@ -196,6 +197,16 @@ size_t jacobi_scratch_elems(int r);
 // kept columns, lam_hat = max(0, w - nu) descending; rank_out (device int).
 int32_t launch_eig_finish(const double *w, const double *V, int r, double nu, double *T,
                           double *lam_hat, int *rank_out, hipStream_t s);
+
+// ---------------------------------------------------------------- test matrix
+// count standard normals (Philox4x32-10 + Box-Muller, a pure function of seed and
+// index) into out.
+int32_t launch_gaussian(uint64_t seed, int64_t count, double *out, hipStream_t s);
+
+// ---------------------------------------------------------------- ceiling probes
+// Time one synthetic kernel keeping one unit busy (0 bf16 MFMA, 1 fp16 MFMA,
+// 2 float64 MFMA, 3 v_exp_f32, 4 device copy); *rate in that unit per second.
+int32_t peak_probe(int which, int iters, double *rate, void *ws, size_t ws_bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- preconditioner apply
 template <class T>

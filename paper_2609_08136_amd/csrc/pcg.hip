@@ -317,16 +317,17 @@ int32_t scatter_cols_d2f(const double *src, int ns, const int *idx, float *dst, 
 // Z = U (gamma .* (U^T R)) + R / lambda_c with gamma_ic = -lh_i / (lambda_c (lh_i + lambda_c)),
 // the cancellation-free form of (lh_i + lambda_c)^{-1} - lambda_c^{-1}.
 template <class T>
-__global__ void gamma_scale_kernel(T *W, int r, int m, const double *lam_hat, const double *lam,
+// damping rho_c = lam[c] + shift (shift: the adaptive damping of the preconditioner)
+__global__ void gamma_scale_kernel(T *W, int r, int m, const double *lam_hat, const double *lam, double shift,
                                    double *inv_lam) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (int64_t)r * m) {
     const int i = (int)(idx / m), c = (int)(idx - (int64_t)i * m);
-    const double lh = lam_hat[i], lc = lam[c];
+    const double lh = lam_hat[i], lc = lam[c] + shift;
     const double g = -lh / (lc * (lh + lc));
     W[idx] = (T)((double)W[idx] * g);
   }
-  if (idx < m) inv_lam[idx] = 1.0 / lam[idx];
+  if (idx < m) inv_lam[idx] = 1.0 / (lam[idx] + shift);
 }
 
 size_t precond_apply_scratch_bytes(int64_t n, int r, int m, int prec) {
@@ -367,7 +368,7 @@ int32_t precond_apply_impl(const nys_precond &P, const double *lambdas, const T 
   }
   const int64_t tot = std::max<int64_t>((int64_t)r * m, m);
   hipLaunchKernelGGL(gamma_scale_kernel<double>, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s, W, r, m,
-                     P.lam_hat, lambdas, inv_lam);
+                     P.lam_hat, lambdas, P.shift, inv_lam);
   NYS_LAUNCH_CHECK();
   if constexpr (sizeof(T) == 8)
     return gemm_nn<double>(U, r, W, m, n, r, m, reinterpret_cast<double *>(Z), m, 1,

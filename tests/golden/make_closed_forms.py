@@ -27,6 +27,23 @@ cases["two_point_solve"] = {
     "X": [[0.0], [1.0]], "sigma": 1.0, "lam": lam, "b": [b1, b2],
     "x": [((1 + lam) * b1 - k * b2) / den, ((1 + lam) * b2 - k * b1) / den],
 }
+# Relative residual (eq. experiment-relative-residual) of the same 2x2 system at
+# perturbed iterates: column 0 is x + e with e = (0.01, -0.03), so the residual is
+# (K + lam I) e; column 1 solves for the right-hand side 3 b with the perturbation
+# 2 e (relative residual 2/3 of column 0's); column 2 has b = 0 and x = e, for which
+# the relative residual is undefined and the absolute norm |(K + lam I) e| is
+# reported instead.  |b| = sqrt(5), so dividing by |b|^2 or leaving out the square
+# roots changes every value.
+e1, e2 = 0.01, -0.03
+r1, r2 = (1 + lam) * e1 + k * e2, k * e1 + (1 + lam) * e2
+xs = cases["two_point_solve"]["x"]
+rn = math.sqrt(r1 * r1 + r2 * r2)
+cases["two_point_relative_residual"] = {
+    "X": [[0.0], [1.0]], "sigma": 1.0, "lam": lam,
+    "B": [[b1, 3 * b1, 0.0], [b2, 3 * b2, 0.0]],
+    "Xsol": [[xs[0] + e1, 3 * xs[0] + 2 * e1, e1], [xs[1] + e2, 3 * xs[1] + 2 * e2, e2]],
+    "relres": [rn / math.sqrt(b1 * b1 + b2 * b2), 2 * rn / (3 * math.sqrt(b1 * b1 + b2 * b2)), rn],
+}
 # Eigenvalues of the 2x2 kernel matrix: 1 + k and 1 - k.
 cases["two_point_eigs"] = {"X": [[0.0], [1.0]], "sigma": 1.0, "eigs": [1.0 + k, 1.0 - k]}
 

@@ -67,7 +67,9 @@ def test_kernel_matvec_argument_errors(lib):
     args = lambda kern, prec=0, d=3, deriv=0: lib.kernel_matvec(kern, deriv, prec, FAKE, 10, FAKE, 10, d, FAKE, 1,
                                                                   FAKE, 1.0, 0.0, FAKE, 0, None)
     assert args(bad_sigma) == nys.EINVAL
+    assert b"sigma" in lib.nys_last_error()
     assert args(bad_kind) == nys.EINVAL
+    assert b"kind" in lib.nys_last_error()
     assert args(k, prec=9) == nys.EINVAL
     assert args(k, d=0) == nys.EINVAL
     assert args(k, d=63, prec=nys.FP32) == nys.EINVAL
@@ -75,7 +77,7 @@ def test_kernel_matvec_argument_errors(lib):
     assert args(k, d=25, prec=nys.BF16X3_D10) == nys.EINVAL
     assert args(k, d=25, prec=nys.F16X3_D10) == nys.EINVAL
     assert args(k, deriv=2) == nys.EINVAL
-    assert b"sigma" in lib.nys_last_error() or True
+    assert b"deriv" in lib.nys_last_error()
     # null workspace
     assert lib.kernel_matvec(k, 0, 0, FAKE, 10, FAKE, 10, 3, FAKE, 1, FAKE, 1.0, 0.0, None, 0, None) == nys.EINVAL
 
@@ -101,8 +103,13 @@ def test_solve_argument_errors(lib):
 
 def test_sketch_and_build_argument_errors(lib):
     k = nys.NysKernel(nys.RBF, 0, 1.0)
-    assert lib.nys_sketch(k, 0, FAKE, 10, 2, FAKE, 11, FAKE, FAKE, 0, None) == nys.EINVAL   # r > n
-    assert lib.nys_sketch(k, 0, FAKE, 10, 2, FAKE, 0, FAKE, FAKE, 0, None) == nys.EINVAL    # r < 1
+    assert lib.nys_sketch(k, 0, FAKE, 10, 2, FAKE, 0, 11, FAKE, FAKE, FAKE, 0, None) == nys.EINVAL   # r > n
+    assert lib.nys_sketch(k, 0, FAKE, 10, 2, FAKE, 0, 0, FAKE, FAKE, FAKE, 0, None) == nys.EINVAL    # r < 1
+    # Q overlapping Omega
+    assert lib.nys_sketch(k, 0, FAKE, 10, 2, FAKE, 0, 3, ctypes.c_void_p(4096 + 8), FAKE, FAKE, 1 << 20,
+                          None) == nys.EINVAL
+    assert lib.nys_test_matrix(0, 0, 3, FAKE, None) == nys.EINVAL
+    assert lib.nys_test_matrix(0, 3, 3, None, None) == nys.EINVAL
     P = nys.NysPrecondC(10, 3, 0, None, None, None, 0.0)
     assert lib.nys_precond_build(FAKE, FAKE, 10, 3, 0, ctypes.byref(P), FAKE, 0, None) == nys.EINVAL
     P2 = nys.NysPrecondC(10, 4, 0, FAKE, None, FAKE, 0.0)
@@ -128,6 +135,8 @@ def test_tile_sources_avoid_packed_fp32_ops():
     assert "-packed-fp32-ops" in build.CFLAGS
     csrc = os.path.join(ROOT, "paper_2609_08136_amd", "csrc")
     for f in os.listdir(csrc):
+        if not f.endswith((".hip", ".h", ".py")):
+            continue
         txt = open(os.path.join(csrc, f)).read()
         assert "v_pk_fma_f32" not in txt and "v_pk_mul_f32" not in txt and "v_pk_add_f32" not in txt
 
@@ -211,3 +220,17 @@ def test_plan_chunks_follow_tuned_widths_and_reject_bad_arguments(lib):
     assert lib.nys_plan_chunks(nys.FP64, 1000, 16, 0, ctypes.byref(tm), ctypes.byref(tail)) == nys.EINVAL
     assert lib.nys_plan_chunks(nys.F16X3_D10, 1000, 25, 10, ctypes.byref(tm), ctypes.byref(tail)) == nys.EINVAL
     assert lib.nys_plan_chunks(nys.FP64, 1000, 16, 10, None, ctypes.byref(tail)) == nys.EINVAL
+
+
+def test_kernel_dot_argument_errors(lib):
+    k = nys.NysKernel(nys.RBF, 0, 1.0)
+    out = ctypes.c_double(0.0)
+    call = lambda kern=k, deriv=0, nr=10, d=3, u=FAKE: lib.kernel_dot(kern, deriv, FAKE, nr, FAKE, 10, d, u, FAKE,
+                                                                    ctypes.byref(out), FAKE, 1 << 20, None)
+    assert call(kern=nys.NysKernel(nys.RBF, 0, -1.0)) == nys.EINVAL
+    assert call(deriv=3) == nys.EINVAL
+    assert call(nr=0) == nys.EINVAL
+    assert call(d=63) == nys.EINVAL
+    assert call(u=None) == nys.EINVAL
+    assert lib.kernel_dot(k, 0, FAKE, 10, FAKE, 10, 3, FAKE, FAKE, ctypes.byref(out), FAKE, 0, None) == nys.ENOMEM
+    assert nys.nys_workspace_bytes(nys.OP_KERNEL_DOT, 1000, 2000, 16) > 0

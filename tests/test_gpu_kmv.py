@@ -1,14 +1,10 @@
 """GPU parity of kernel_matvec against the CPU float64 oracle, element by element.
 
-Tolerances are error bounds written against |K| |V| (row by row), derived from
-the arithmetic of each precision:
-  * the exponent t = kappa (2 x.y - |x|^2 - |y|^2) is formed by one MFMA chain;
-    its absolute error is at most c u kappa (|x| + |y|)^2, so each kernel value
-    carries a relative error of about u (1 + kappa_max (|x| + |y|)^2);
-  * accumulation over the nc columns adds at most (nc/4 + 16) u relative to
-    |K| |V| (sequential per-lane sums of nc/4 terms, then a 4-way reduction);
-  * BF16X3 splits both distance operands into bf16 pairs (about 2^-16 relative
-    per product) and, with >= 16 columns, also k and V.
+Every case runs twice, with random-sign V and with V >= 0 (where |K| |V| = |K V|, so
+the bound is relative to the result itself).  The bounds (tests/kmv_bounds.py) are
+derived from the arithmetic of each precision, pair by pair, and each case also
+asserts that its largest tolerance is below a tenth of its largest |reference|
+(an all-zero output, or a product that drops a split part, fails).
 """
 import math
 
@@ -16,31 +12,13 @@ import numpy as np
 import pytest
 import torch
 
+import kmv_bounds as kb
 import nys_inputs as ni
 import oracle as o
 
 pytestmark = pytest.mark.gpu
 
-U = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -16, 3: 2.0 ** -16, 4: 2.0 ** -16, 5: 2.0 ** -16}
-
-
-def bound(Xr, Xc, V, kind, sigma, prec, deriv=0):
-    """Row-wise bound on |gpu - oracle| from the arithmetic of `prec`."""
-    K = o.kernel_dsigma_matrix(Xr, Xc, kind, sigma) if deriv else o.kernel_matrix(Xr, Xc, kind, sigma)
-    mu = Xc.mean(0)
-    nr_ = np.linalg.norm(Xr - mu, axis=1)
-    nc_ = np.linalg.norm(Xc - mu, axis=1)
-    span = (nr_.max() + nc_.max()) ** 2
-    kap = 1.0 / (2 * sigma * sigma) if kind == o.RBF else 1.0
-    u = U[prec]
-    ent = 16 * u * (1.0 + kap * span)
-    if kind == o.LAPLACIAN:
-        # d = sqrt(d^2): an absolute error e in d^2 gives sqrt(e) in d near d = 0
-        ent = 16 * u * (1.0 + kap * span) + math.sqrt(16 * u * span) / sigma
-    if deriv:
-        ent *= 4
-    acc = (Xc.shape[0] / 4 + 16) * (2.0 ** -53 if prec == 0 else 2.0 ** -24)
-    return (ent + acc) * (np.abs(K) @ np.abs(V)) + 1e-300
+GUARD = 0.1
 
 
 def run(nys, Xr, Xc, V, kind, sigma, prec, deriv=0, alpha=1.0, beta=0.0, out=None):
@@ -70,13 +48,19 @@ def check(nys, n_r, n_c, d, m, kind, prec, seed=0, same=True, deriv=0, heavy=Fal
     if prec != 0:
         V = V.astype(np.float32).astype(np.float64)   # the float32 input the GPU sees
     sigma = math.sqrt(d)
-    print(f"case n_r={n_r} n_c={Xc.shape[0]} d={d} m={m} kind={kind} prec={prec} deriv={deriv}", flush=True)
-    got = run(nys, Xr, Xc, V, kind, sigma, prec, deriv)
-    ref = o.kernel_matvec(Xr, Xc, V, kind, sigma, deriv)
-    tol = bound(Xr, Xc, V, kind, sigma, prec, deriv)
-    err = np.abs(got - ref)
-    worst = float(np.max(err / tol))
-    assert worst <= 1.0, f"max err/bound = {worst:.3g} (max abs err {err.max():.3g})"
+    A, K = kb.entry_abs_bound(Xr, Xc, kind, sigma, prec, m, deriv, same=Xc is Xr)
+    for name, VV in (("random-sign", V), ("nonnegative", np.abs(V))):
+        print(f"case n_r={n_r} n_c={Xc.shape[0]} d={d} m={m} kind={kind} prec={prec} deriv={deriv} V {name}",
+              flush=True)
+        got = run(nys, Xr, Xc, VV, kind, sigma, prec, deriv)
+        ref = K @ VV
+        tol = kb.product_bound(Xr, Xc, VV, kind, sigma, prec, deriv, same=Xc is Xr)
+        err = np.abs(got - ref)
+        worst = float(np.max(err / tol))
+        g = kb.guard(tol, ref)
+        print(f"  max err/bound {worst:.3g}, bound guard {g:.3g}", flush=True)
+        assert g < GUARD, f"bound too loose to fail: max tol / max |ref| = {g:.3g}"
+        assert worst <= 1.0, f"max err/bound = {worst:.3g} (max abs err {err.max():.3g})"
     return got, ref
 
 
@@ -135,9 +119,12 @@ def test_matvec_duplicate_points(nys, prec, kind, m):
         V = V.astype(np.float32).astype(np.float64)
     sigma = 4.0
     print(f"case duplicates prec={prec} kind={kind} m={m}", flush=True)
-    got = run(nys, X, X, V, kind, sigma, prec)
-    ref = o.kernel_matvec(X, X, V, kind, sigma)
-    assert np.max(np.abs(got - ref) / bound(X, X, V, kind, sigma, prec)) <= 1.0
+    for VV in (V, np.abs(V)):
+        got = run(nys, X, X, VV, kind, sigma, prec)
+        ref = o.kernel_matvec(X, X, VV, kind, sigma)
+        tol = kb.product_bound(X, X, VV, kind, sigma, prec, same=True)
+        assert kb.guard(tol, ref) < GUARD
+        assert np.max(np.abs(got - ref) / tol) <= 1.0
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -195,31 +182,87 @@ def test_matvec_deterministic(nys):
         assert np.array_equal(a, b)
 
 
+def _sampled_bound(X, rows, V, sigma, prec):
+    """Bound and reference for sampled rows of an n x n product (row blocks of the
+    per-pair entry bound against all n points)."""
+    A, K = kb.entry_abs_bound(X[rows], X, o.RBF, sigma, prec, V.shape[1], 0)
+    for t, i in enumerate(rows):
+        A[t, i] = 0.0                                    # K_ii = 1 exactly (symmetric product)
+        K[t, i] = 1.0
+    return K @ V, kb.bound_from(A, K, V, prec, V.shape[1], 0)
+
+
 def test_matvec_large_sampled_rows(nys):
     """Full-size check on sampled rows: n = 1e6 points, d = 16 (the batched workload's
-    point set), one and 512 columns in BF16X3; rows sampled and recomputed by the
-    oracle one by one."""
+    point set), 1 ... 512 columns, random-sign and non-negative V; 24 rows sampled and
+    recomputed by the oracle one by one against all 1e6 points."""
     w = ni.batched_lambda_grid(0, n=1_000_000, nrhs=2, nlam=1)
     X = w.X
     dev = torch.device("cuda")
     tX = torch.from_numpy(X).to(dev)
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(X.shape[0], 24, replace=False))
-    for m, prec in ((1, 2), (512, 2), (512, 3), (512, 4), (64, 4), (512, 5), (40, 5)):
-        V = rng.standard_normal((X.shape[0], m)).astype(np.float32)
-        tV = torch.from_numpy(V).to(dev)
-        print(f"case n=1e6 d=16 m={m} prec={prec}", flush=True)
-        out = nys.kernel_matvec(tX, tX, tV, o.RBF, w.sigma, prec)
-        torch.cuda.synchronize()
-        got = out[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
-        ref = o.kernel_matvec_rows(X[rows], X, V.astype(np.float64), o.RBF, w.sigma)
-        Kabs = o.kernel_matvec_rows(X[rows], X, np.abs(V).astype(np.float64), o.RBF, w.sigma)
-        mu = X.mean(0)
-        span = (np.linalg.norm(X[rows] - mu, axis=1).max() + np.linalg.norm(X - mu, axis=1).max()) ** 2
-        kap = 1 / (2 * w.sigma ** 2)
-        tol = (16 * 2.0 ** -16 * (1 + kap * span) + (X.shape[0] / 4 + 16) * 2.0 ** -24) * Kabs
-        assert np.max(np.abs(got - ref) / tol) <= 1.0
-        del out, tV
+    trows = torch.from_numpy(rows).to(dev)
+    Vs = {}
+    for m, prec in ((1, 2), (512, 2), (256, 3), (128, 4), (64, 4), (512, 5), (40, 5), (1, 5), (1, 0), (64, 0)):
+        if m not in Vs:
+            Vs[m] = rng.standard_normal((X.shape[0], m)).astype(np.float32).astype(np.float64)
+        V = Vs[m]
+        for name, VV in (("random-sign", V), ("nonnegative", np.abs(V))):
+            dt = torch.float64 if prec == 0 else torch.float32
+            tV = torch.from_numpy(VV).to(dev, dt)
+            print(f"case n=1e6 d=16 m={m} prec={prec} V {name}", flush=True)
+            out = nys.kernel_matvec(tX, tX, tV, o.RBF, w.sigma, prec)
+            torch.cuda.synchronize()
+            got = out[trows].double().cpu().numpy()
+            ref, tol = _sampled_bound(X, rows, VV, w.sigma, prec)
+            worst = float(np.max(np.abs(got - ref) / tol))
+            g = kb.guard(tol, ref)
+            print(f"  max err/bound {worst:.3g}, bound guard {g:.3g}", flush=True)
+            assert g < GUARD
+            assert worst <= 1.0
+            del out, tV
+
+
+@pytest.mark.parametrize("prec,widths", [(5, (16, 32, 64, 128, 256)), (2, (32, 256)), (0, (16, 128, 256))])
+def test_unit_vector_entries_every_width_n1e6(nys, prec, widths):
+    """Single kernel entries of the full-size point set (n = 1e6, d = 16, sigma = 4)
+    through every column-chunk width: V holds unit vectors e_j, so each output is one
+    entry K_ij, held to the per-pair entry bound (no accumulation error).  The
+    headline tile (fp16 product, 256-column chunk) is among them."""
+    w = ni.batched_lambda_grid(0, n=1_000_000, nrhs=2, nlam=1)
+    X = w.X
+    n = X.shape[0]
+    dev = torch.device("cuda")
+    tX = torch.from_numpy(X).to(dev)
+    rng = np.random.default_rng(31)
+    rows = np.sort(rng.choice(n, 32, replace=False))
+    trows = torch.from_numpy(rows).to(dev)
+    dt = torch.float64 if prec == 0 else torch.float32
+    try:
+        for tm in widths:
+            nys.nys_set_tile(prec, 1, 1024, tm)
+            m = tm
+            J = rng.choice(n, m, replace=False)
+            J[:4] = rows[:4]                                # some diagonal entries too
+            tV = torch.zeros((n, m), dtype=dt, device=dev)
+            tV[torch.from_numpy(J).to(dev), torch.arange(m, device=dev)] = 1.0
+            print(f"case unit vectors n=1e6 prec={prec} width={tm}", flush=True)
+            out = nys.kernel_matvec(tX, tX, tV, o.RBF, w.sigma, prec)
+            torch.cuda.synchronize()
+            got = out[trows].double().cpu().numpy()
+            A, K = kb.entry_abs_bound(X[rows], X[J], o.RBF, w.sigma, prec, m, 0, mu=X.mean(0))
+            diag = rows[:, None] == J[None, :]
+            K[diag] = 1.0
+            A[diag] = 0.0
+            err = np.abs(got - K)
+            worst = float(np.max(err / (A + 1e-300)))
+            print(f"  max err/bound {worst:.3g}, max relative entry error {np.max(err / K):.3g}", flush=True)
+            assert worst <= 1.0
+            assert np.all(got[diag] == 1.0) or prec != 0
+            del out, tV
+    finally:
+        nys.nys_clear_tiles()
 
 
 def test_six_term_distance_is_more_accurate(nys):
@@ -285,9 +328,37 @@ def test_autotune_records_a_valid_width(nys):
         V = rng.standard_normal((6000, 80)).astype(np.float32).astype(np.float64)
         got = run(nys, Xn, Xn, V, o.RBF, 4.0, 5)
         ref = o.kernel_matvec(Xn, Xn, V, o.RBF, 4.0)
-        assert np.max(np.abs(got - ref) / bound(Xn, Xn, V, o.RBF, 4.0, 5, 0)) <= 1.0
+        tol = kb.product_bound(Xn, Xn, V, o.RBF, 4.0, 5, 0, same=True)
+        assert kb.guard(tol, ref) < GUARD
+        assert np.max(np.abs(got - ref) / tol) <= 1.0
         t0, _ = nys.nys_autotune(X, o.RBF, 4.0, nys.F16X3_D10, 1, reps=1)   # one column: fp16 tile too
         assert t0 in (16, 32)
         assert nys.nys_autotune(X, o.RBF, 4.0, nys.FP64, 3, reps=1)[0] == 0  # row-sum tile: nothing to tune
     finally:
         nys.nys_clear_tiles()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+@pytest.mark.parametrize("where", ["rows", "cols", "inf"])
+def test_non_finite_points_are_rejected(nys, prec, kind, where):
+    """A NaN or Inf coordinate in either point set returns NYS_ENUMERIC instead of a
+    silently wrong product (a NaN column point would turn the centre, and with it every
+    packed point, into NaN)."""
+    rng = np.random.default_rng(40)
+    Xr = rng.standard_normal((300, 8))
+    Xc = rng.standard_normal((500, 8))
+    if where == "rows":
+        Xr[17, 3] = np.nan
+    elif where == "cols":
+        Xc[250, 0] = np.nan
+    else:
+        Xc[3, 7] = np.inf
+    V = rng.standard_normal((500, 20))
+    print(f"case non-finite prec={prec} kind={kind} where={where}", flush=True)
+    with pytest.raises(nys.NysError) as ei:
+        run(nys, Xr, Xc, V, kind, 2.0, prec)
+    assert ei.value.code == nys.ENUMERIC
+    # a finite input on the same buffers still works afterwards
+    got = run(nys, np.nan_to_num(Xr, posinf=0.0), np.nan_to_num(Xc, posinf=0.0), V, kind, 2.0, prec)
+    assert np.all(np.isfinite(got))

@@ -118,6 +118,18 @@ def test_direct_solve_vs_lapack_lu():
     assert o.relative_residual(K, x, w.B[:, 0], w.lambdas[0])[0] < 1e-13
 
 
+def test_relative_residual_closed_form():
+    """Per-column |(K + lam I) x - b| / |b| at perturbed iterates of the two-point system
+    (values from the closed form in tests/golden), including a b = 0 column."""
+    g = golden()["two_point_relative_residual"]
+    X = np.array(g["X"])
+    K = o.kernel_matrix(X, X, o.RBF, g["sigma"])
+    rel = o.relative_residual(K, np.array(g["Xsol"]), np.array(g["B"]), g["lam"])
+    assert np.allclose(rel, g["relres"], rtol=1e-12, atol=0)
+    one = o.relative_residual(K, np.array(g["Xsol"])[:, 0], np.array(g["B"])[:, 0], g["lam"])
+    assert one.shape == (1,) and abs(one[0] - g["relres"][0]) <= 1e-12 * g["relres"][0]
+
+
 # ---------------------------------------------------------------- Nystrom
 
 def _spd_test_matrix(n, seed, cond=1e3):
@@ -359,3 +371,105 @@ def test_mutant_gradient_sign_is_caught():
     mutant = +float(a @ x)                                           # sign flipped
     assert abs(lam * mutant - fd) > 1e-3 * abs(fd)
     assert abs(lam * dlam - fd) <= 1e-5 * abs(fd)
+
+
+@pytest.mark.parametrize("mistake", ["norm_squared", "no_square_root"])
+def test_mutant_relative_residual_normalisation_is_caught(mistake):
+    g = golden()["two_point_relative_residual"]
+    X = np.array(g["X"])
+    K = o.kernel_matrix(X, X, o.RBF, g["sigma"])
+    x, b = np.array(g["Xsol"])[:, :2], np.array(g["B"])[:, :2]
+    res = K @ x + g["lam"] * x - b
+    if mistake == "norm_squared":
+        mutant = np.linalg.norm(res, axis=0) / np.sum(b * b, axis=0)
+    else:
+        mutant = np.sum(res * res, axis=0) / np.sum(b * b, axis=0)
+    assert np.max(np.abs(mutant - np.array(g["relres"][:2]))) > 1e-2 * max(g["relres"][:2])
+
+
+# ---------------------------------------------------------------- counter-based test matrix
+
+def test_philox_known_answers():
+    """Philox4x32-10 against the known-answer vectors published with the generator's
+    reference implementation (all-zero counter and key; the hexadecimal digits of pi)."""
+    from oracle import philox as ph
+    kat = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+           ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+            (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, want in kat:
+        got = ph.philox4x32_10(np.array(ctr, dtype=np.uint64), np.array(key, dtype=np.uint64))
+        assert [int(v) for v in got] == list(want)
+
+
+def test_philox_gaussian_test_matrix_distribution():
+    """The oracle's seeded test matrix is standard normal (Kolmogorov-Smirnov against
+    the normal CDF), its cosine and sine halves are uncorrelated, different seeds give
+    different draws, and a row range is a pure function of (seed, index)."""
+    import scipy.stats as st
+    from oracle import philox as ph
+    Z = ph.gaussian_test_matrix(400, 250, 12345)
+    assert st.kstest(Z.reshape(-1), "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(Z.reshape(-1)[0::2], Z.reshape(-1)[1::2])[0, 1]) < 0.02
+    assert not np.allclose(Z, ph.gaussian_test_matrix(400, 250, 12346))
+    assert np.array_equal(ph.gaussian_test_matrix(401, 250, 12345)[:400], Z)
+
+
+# ---------------------------------------------------------------- rank adaptation, damping modes
+
+def test_power_error_against_dense_spectrum():
+    """The power estimate of |K - K_hat|_2 approaches the largest eigenvalue of the
+    PSD residual from below (dense eigvalsh on a tiny case with a spectral gap)."""
+    w = ni.small_problem(300, 4, seed=21, r=12)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, nu = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(300, 12, 21))
+    E = K - o.nystrom_matrix(U, lh)
+    ev = np.linalg.eigvalsh(0.5 * (E + E.T))
+    v0 = np.random.default_rng(5).standard_normal(300)
+    e3 = o.power_error(lambda V: K @ V, U, lh, v0, 3)
+    e30 = o.power_error(lambda V: K @ V, U, lh, v0, 30)
+    assert e3 <= ev[-1] * (1 + 1e-10) and e30 <= ev[-1] * (1 + 1e-10)
+    assert e30 >= 0.999 * ev[-1] and e30 >= e3 - 1e-12 * ev[-1]
+
+
+def test_rank_adaptation_stops_at_exact_low_rank():
+    """A rank-5 PSD matrix (linear kernel of 5-dimensional points): from rank 2 the
+    rank doubles to 4 (error still large), then 8 >= 5 recovers K up to the shift,
+    and the loop stops there; with rank_max 4 it stops at 4."""
+    rng = np.random.default_rng(22)
+    Z = rng.standard_normal((200, 5))
+    K = Z @ Z.T
+    Om = rng.standard_normal((200, 32))
+    v0 = rng.standard_normal(200)
+    U, lh, nu, l, err = o.nystrom_adaptive(lambda V: K @ V, Om, 2, 32, 10, 1e-2, v0)
+    assert l == 8 and err <= 1e-8 * lh[0]
+    assert np.max(np.abs(o.nystrom_matrix(U, lh) - K)) <= 1e-8 * lh[0]
+    U4, lh4, _, l4, err4 = o.nystrom_adaptive(lambda V: K @ V, Om, 2, 4, 10, 1e-2, v0)
+    assert l4 == 4 and err4 > 1e-2 * lh4[0]
+    _, _, _, l1, _ = o.nystrom_adaptive(lambda V: K @ V, Om, 2, None, 10, 1e-2, v0)
+    assert l1 == 2
+
+
+def test_adaptive_damping_preconditioner():
+    """P = K_hat + (lam + lam_hat_min) I: the closed-form apply is the dense inverse, and
+    the preconditioned spectrum lies in [lam / (lam + lam_hat_min), 1 + |K - K_hat| /
+    (lam + lam_hat_min)] (K_hat <= K up to nu)."""
+    w = ni.small_problem(250, 4, seed=23, r=20)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, nu = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(250, 20, 23))
+    lam = 0.05
+    sh = o.damping_shift(lh, "adaptive")
+    assert sh == lh[-1] and o.damping_shift(lh, "non_adaptive") == 0.0
+    P = o.nystrom_matrix(U, lh) + (lam + sh) * np.eye(250)
+    R = np.random.default_rng(6).standard_normal((250, 3))
+    assert np.allclose(o.precond_apply(U, lh, lam, R, shift=sh), np.linalg.solve(P, R), rtol=1e-9, atol=1e-12)
+    A = K + lam * np.eye(250)
+    L = np.linalg.cholesky(P)
+    M = np.linalg.solve(L, np.linalg.solve(L, A).T).T
+    ev = np.linalg.eigvalsh(0.5 * (M + M.T))
+    Enorm = np.linalg.norm(K - o.nystrom_matrix(U, lh), 2)
+    assert ev[0] >= lam / (lam + sh) * (1 - 1e-9) - nu / lam
+    assert ev[-1] <= 1 + Enorm / (lam + sh) + 1e-9
+    # the adaptive preconditioner still gives the direct solution through PCG
+    b = w.B[:, 0]
+    x, it, _ = o.pcg(lambda v: A @ v, b, lambda r: o.precond_apply(U, lh, lam, r, shift=sh), tol=1e-12)
+    assert np.linalg.norm(x - o.direct_solve(K, b, lam)) <= 1e-9 * np.linalg.norm(x)
