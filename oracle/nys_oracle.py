@@ -344,3 +344,57 @@ def validation_loss_grad(X, y, Xv, yv, kind, sigma, lam):
     dKvt = kernel_dsigma_matrix(Xv, X, kind, sigma)
     dsig = float(e @ (dKvt @ x)) - float(a @ (dK @ x))
     return L, dlam, dsig, x, a
+
+
+# ---------------------------------------------------------------------------
+# Unrolled differentiation (section "Differentiating Through the Solver")
+# ---------------------------------------------------------------------------
+
+def unrolled_validation_grad(X, y, Xv, yv, kind, sigma, lam, U, lam_hat, iters: int):
+    """The validation loss after exactly `iters` textbook PCG iterations from x0 = 0,
+    L_k = mean((K_vt x_k - y_v)^2), and its gradient with respect to (lambda, sigma)
+    by differentiating through the iterations (reverse-mode automatic differentiation
+    in float64, PyTorch on the CPU): the unrolled alternative to the implicit adjoint
+    that the paper's differentiation section describes.  The preconditioner P =
+    U diag(lam_hat) U^T + lam I is held fixed (its lam a constant, U and lam_hat
+    given), as in the adjoint; as iters grows the result tends to the exact gradient
+    of validation_loss_grad.  Returns (L_k, dL_k/dlambda, dL_k/dsigma)."""
+    import torch
+
+    t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64))
+    D, Dv = t(squared_distances(X, X)), t(squared_distances(Xv, X))
+    lam_t = torch.tensor(float(lam), dtype=torch.float64, requires_grad=True)
+    sig_t = torch.tensor(float(sigma), dtype=torch.float64, requires_grad=True)
+
+    def kmat(Dm):
+        if kind == RBF:
+            return torch.exp(-Dm / (2.0 * sig_t * sig_t))
+        return torch.exp(-torch.sqrt(Dm) / sig_t)
+
+    K, Kvt = kmat(D), kmat(Dv)
+    Ut, lh = t(U), t(lam_hat)
+    lam0 = float(lam)
+
+    def pinv(r):
+        w = Ut.T @ r
+        return Ut @ (w / (lh + lam0)) + (r - Ut @ w) / lam0
+
+    b = t(y).reshape(-1)
+    x = torch.zeros_like(b)
+    r = b.clone()
+    z = pinv(r)
+    p = z.clone()
+    rho = r @ z
+    for _ in range(iters):
+        w = K @ p + lam_t * p
+        alpha = rho / (p @ w)
+        x = x + alpha * p
+        r = r - alpha * w
+        z = pinv(r)
+        rho_new = r @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    res = Kvt @ x - t(yv).reshape(-1)
+    L = (res @ res) / res.shape[0]
+    L.backward()
+    return float(L.detach()), float(lam_t.grad), float(sig_t.grad)

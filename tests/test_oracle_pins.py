@@ -473,3 +473,58 @@ def test_adaptive_damping_preconditioner():
     b = w.B[:, 0]
     x, it, _ = o.pcg(lambda v: A @ v, b, lambda r: o.precond_apply(U, lh, lam, r, shift=sh), tol=1e-12)
     assert np.linalg.norm(x - o.direct_solve(K, b, lam)) <= 1e-9 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------- unrolled differentiation
+
+@pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
+def test_unrolled_gradient_tends_to_the_exact_gradient(kind):
+    """Differentiating through k PCG iterations: after enough iterations the unrolled
+    gradient is the implicit (exact) one of validation_loss_grad."""
+    w = ni.small_problem(260, 4, seed=51, kind=kind, r=20)
+    X, y, Xv, yv = w.X[:200], w.B[:200, 0], w.X[200:], w.B[200:, 0]
+    lam, sig = 0.3, 1.4
+    K = o.kernel_matrix(X, X, kind, sig)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(200, 20, 51))
+    L, dlam, dsig, _, _ = o.validation_loss_grad(X, y, Xv, yv, kind, sig, lam)
+    Lk, gl, gs = o.unrolled_validation_grad(X, y, Xv, yv, kind, sig, lam, U, lh, 60)
+    assert Lk == pytest.approx(L, rel=1e-10)
+    assert gl == pytest.approx(dlam, rel=1e-8)
+    assert gs == pytest.approx(dsig, rel=1e-8)
+
+
+def test_unrolled_gradient_matches_differences_of_the_truncated_loss():
+    """After 3 iterations (far from converged) the unrolled gradient is the derivative
+    of the 3-iteration loss itself: central differences of L_3 in lambda and sigma
+    (with the preconditioner fixed) agree, and both differ from the exact gradient."""
+    w = ni.small_problem(220, 3, seed=52, r=10)
+    X, y, Xv, yv = w.X[:180], w.B[:180, 0], w.X[180:], w.B[180:, 0]
+    lam, sig = 0.2, 1.1
+    K = o.kernel_matrix(X, X, o.RBF, sig)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(180, 10, 52))
+
+    def L3(lm, sg):
+        # the same truncated solve with the preconditioner's damping held at lam
+        Km = o.kernel_matrix(X, X, o.RBF, sg)
+        x = np.zeros(180)
+        r = y.copy()
+        z = o.precond_apply(U, lh, lam, r)
+        p, rho = z.copy(), r @ z
+        for _ in range(3):
+            wv = Km @ p + lm * p
+            al = rho / (p @ wv)
+            x, r = x + al * p, r - al * wv
+            z = o.precond_apply(U, lh, lam, r)
+            rn = r @ z
+            p, rho = z + (rn / rho) * p, rn
+        res = o.kernel_matrix(Xv, X, o.RBF, sg) @ x - yv
+        return float(res @ res) / len(yv)
+
+    _, gl, gs = o.unrolled_validation_grad(X, y, Xv, yv, o.RBF, sig, lam, U, lh, 3)
+    h = 1e-6
+    fl = (L3(lam + h, sig) - L3(lam - h, sig)) / (2 * h)
+    fs = (L3(lam, sig + h) - L3(lam, sig - h)) / (2 * h)
+    assert gl == pytest.approx(fl, rel=1e-6)
+    assert gs == pytest.approx(fs, rel=1e-6)
+    _, dlam, dsig, _, _ = o.validation_loss_grad(X, y, Xv, yv, o.RBF, sig, lam)
+    assert abs(gs - dsig) > 1e-4 * abs(dsig)
