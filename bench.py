@@ -80,6 +80,11 @@ def parse():
                     help="with --kmv-only: first run one plain 1 GiB device copy, whose HBM counter readings "
                          "scale the kernel's (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--ridge-n", type=int, default=65536, help="ridge_ratio: rows of X")
+    ap.add_argument("--ridge-p", type=int, default=0, help="ridge_ratio: columns of X (0: = rows)")
+    ap.add_argument("--ridge-alpha", type=float, default=2.0, help="ridge_ratio: spectral decay")
+    ap.add_argument("--ridge-lambda", type=float, default=1e-6, help="ridge_ratio: regularisation")
+    ap.add_argument("--ridge-rank", type=int, default=128, help="ridge_ratio: Nystrom rank")
     ap.add_argument("--prec", default="f16x3_d10", choices=["bf16x3", "bf16x3_d6", "bf16x3_d10", "f16x3_d10", "fp32"],
                     help="kernel-product precision of the batched workload")
     ap.add_argument("--no-autotune", action="store_true",
@@ -88,7 +93,7 @@ def parse():
                     help="JSON cache of autotuned chunk widths")
     ap.add_argument("--workload", default="batched_lambda_grid",
                     choices=["batched_lambda_grid", "plain_fp64", "matrix_free_fp32", "precision_variant",
-                             "differentiation", "grid_vs_fp32", "cg_ratio"],
+                             "differentiation", "grid_vs_fp32", "cg_ratio", "ridge_ratio"],
                     help="batched_lambda_grid is the headline workload; the others are recorded separately")
     return ap.parse_args()
 
@@ -186,6 +191,8 @@ def run_other(args):
                    runs=res, speedup_vs_fp32=round(res["fp32"]["seconds"] / res["bf16x3"]["seconds"], 3))
     elif wl in ("grid_vs_fp32", "cg_ratio"):
         out.update(grid_or_cg(args, nys, torch, ni, dev, T))
+    elif wl == "ridge_ratio":
+        out.update(ridge_ratio(args, nys, torch, ni, dev))
     else:  # differentiation
         from paper_2609_08136_amd import autograd as ag
         w = ni.differentiation(args.seed)
@@ -300,6 +307,70 @@ def grid_or_cg(args, nys, torch, ni, dev, T):
             "config": {"workload": "cg_ratio", "n": w.n, "d": w.d, "rank": w.r, "tol": w.tol,
                        "lambda": w.lambdas[0]},
             "runs": res, "median_s": med}
+
+
+def ridge_ratio(args, nys, torch, ni, dev):
+    """CG time / NysPCG time on the paper's ridge problem (section "Large-Scale Ridge
+    Regression with NysPCG": X = U Sigma V^T from SORF factors, y = U g / |g|), normal
+    matrix applied through X and X^T, tolerance 1e-6 (the paper's calibrated ridge
+    tolerance), rank-128 Nystrom preconditioner built inside the timed NysPCG region,
+    median and min-max over the seeds (three by default)."""
+    import numpy as np
+
+    n = args.ridge_n
+    p = args.ridge_p or n
+    alpha, lam, rank, tol = args.ridge_alpha, args.ridge_lambda, args.ridge_rank, 1e-6
+    seeds = [int(v) for v in args.seeds.split(",") if v.strip()] or [0, 1, 2]
+    runs = {"nyspcg": [], "cg": []}
+
+    def nyspcg(X, y, seed, max_iters):
+        Y, Q = nys.nys_ridge_sketch(X, None, seed=seed, r=rank)
+        P = nys.nys_precond_build(Y, Q, with_fp32=False)
+        del Y, Q
+        return nys.nys_ridge_solve(X, y, lam, P, tol=tol, max_iters=max_iters, check_true=True)
+
+    def cg(X, y, seed, max_iters):
+        return nys.nys_ridge_solve(X, y, lam, None, tol=tol, max_iters=max_iters, check_true=True)
+
+    for seed in seeds:
+        (X, y), t_gen = _timed(torch, lambda: ni.ridge_problem_device(n, p, alpha, seed, dev))
+        phase(f"ridge seed {seed}: X {n} x {p} built on the device in {t_gen:.1f} s")
+        for name, fn, cap in (("nyspcg", nyspcg, 5000), ("cg", cg, 20000)):
+            fn(X, y, seed, 3)                                                          # warm-up
+            (W, info, rc), t = _timed(torch, lambda: fn(X, y, seed, cap))
+            r = {"seed": seed, "seconds": round(t, 4), "iters": info[0]["iters"], "status": rc,
+                 "relres_recursive": info[0]["relres_recursive"], "relres_true": info[0]["relres_true"]}
+            runs[name].append(r)
+            phase(f"ridge seed {seed} {name}: {r}")
+            del W
+        del X, y
+        torch.cuda.empty_cache()
+    med = {k: statistics.median(r["seconds"] for r in v) for k, v in runs.items()}
+    rng = {k: [min(r["seconds"] for r in v), max(r["seconds"] for r in v)] for k, v in runs.items()}
+    cg_capped = any(r["status"] != nys.OK for r in runs["cg"])
+    out = {"metric": f"CG time / NysPCG time, ridge n={n} p={p} alpha={alpha:g} lambda={lam:g}, rel. residual 1e-6",
+           "value": round(med["cg"] / med["nyspcg"], 3), "unit": "ratio", "higher_is_better": True,
+           "ms_per_step": round(med["nyspcg"] * 1e3, 2), "dtype": "f64", "steps": len(seeds),
+           "config": {"workload": "ridge_ratio", "n": n, "p": p, "alpha": alpha, "lambda": lam, "rank": rank,
+                      "tol": tol, "seeds": seeds},
+           "median_s": med, "min_max_s": rng, "runs": runs,
+           "cg_lower_bound": cg_capped,
+           "paper_context": "7.23x on one H200 at n = p = 2^16, alpha 2, lambda 1e-6 (another machine)"}
+    if not args.no_cpu:
+        import oracle as o
+
+        pr = ni.ridge_problem(4096, 4096, alpha, seed=seeds[0])
+        t0 = time.perf_counter()
+        U, lh, _ = o.nystrom(o.ridge_normal_apply(pr.X), ni.gaussian_test_matrix(4096, rank, seeds[0]))
+        A = o.ridge_normal_apply(pr.X)
+        b = pr.X.T @ pr.y
+        _, it, _ = o.pcg(lambda v: A(v) + lam * v, b, lambda r: o.precond_apply(U, lh, lam, r), tol=tol,
+                         max_iters=5000)
+        t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(t_cpu, 3), "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": f"oracle NysPCG (rank {rank}, float64 NumPy) on the same recipe at "
+                                         f"n = p = 4096 on the host: {it} iterations"}
+    return out
 
 
 def log(args, *a):

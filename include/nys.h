@@ -96,7 +96,9 @@ typedef enum {
   NYS_OP_BACKWARD = 5,
   NYS_OP_AUTOTUNE = 6,
   NYS_OP_KERNEL_DOT = 7,
-  NYS_OP_PRECOND_ADAPTIVE = 8
+  NYS_OP_PRECOND_ADAPTIVE = 8,
+  NYS_OP_RIDGE_SKETCH = 9,
+  NYS_OP_RIDGE_SOLVE = 10
 } nys_op;
 
 /* Kernel function: kind (nys_kind) and bandwidth sigma > 0. */
@@ -191,6 +193,11 @@ typedef struct {
  *                  cycles use max(refine_reduction, min(0.5, g)) with g the
  *                  true-residual reduction the previous cycle achieved (modes
  *                  0, 1) or the drift rescaling above (mode 2)
+ *    refine_join   refine_every == 0: when one column is due, every column whose
+ *                  recursive residual is within refine_join times its own cycle
+ *                  target joins the same float64 product (0: 3; else >= 1).
+ *                  Larger values trade restarts a little early for fewer float64
+ *                  products, each of which costs a full sweep over the n^2 pairs.
  */
 typedef struct {
   double tol;
@@ -201,6 +208,7 @@ typedef struct {
   int32_t check_true;
   int32_t max_refinements;
   double refine_reduction;
+  double refine_join;
 } nys_pcg_opts;
 
 /* Per-column result. */
@@ -223,6 +231,9 @@ typedef struct {
  *   AUTOTUNE:      n = n_rows, n2 = n, d, m, prec
  *   KERNEL_DOT:    n = nr, n2 = nc, d
  *   PRECOND_ADAPTIVE: n, d, r = rank_max, prec
+ *   RIDGE_SKETCH:  n = rows of X, n2 = p, r
+ *   RIDGE_SOLVE:   n = rows of X, n2 = p, d = nrhs, r (0 if no preconditioner),
+ *                  m = nlam * nrhs
  * Returns NYS_OK and *bytes, or NYS_EINVAL. */
 int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_t r, int32_t m,
                             int32_t prec, size_t *bytes);
@@ -422,6 +433,30 @@ int32_t nys_plan_chunks(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *
  * timed one(s) on `stream`; synchronises the stream.  NYS_EINVAL for which outside
  * 0..4 or a null pointer, NYS_ENOMEM for a smaller workspace. */
 int32_t nys_peak_probe(int32_t which, int32_t iters, double *rate, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- ridge regression (the paper's own NysPCG workload) --------------------
+ * The regularised normal equations (X^T X + lambda I) w = X^T y of ridge regression
+ * (section "Large-Scale Ridge Regression with NysPCG", eq. experiment-ridge), with the
+ * normal matrix applied matrix-free through two float64 products with the dense data
+ * matrix X (n x p, row-major, device) and never formed; the products are rocBLAS
+ * GEMMs.  The Nystrom preconditioner of X^T X is built from nys_ridge_sketch's (Y, Q)
+ * by nys_precond_build (or used with nys_precond_apply) exactly as for a kernel.
+ *
+ * nys_ridge_sketch: Q = the orthonormalised p x r test matrix (Omega, read only, or
+ * drawn from `seed` when NULL, as nys_sketch), Y = X^T (X Q) (p x r).  Requires
+ * 1 <= r <= min(p, 1024).  Synchronises the stream.
+ *
+ * nys_ridge_solve: NysPCG (or CG when P == NULL) for every column c = l nrhs + j:
+ * (X^T X + lambdas[l] I) w = X^T y_j, y the n x nrhs targets (device).  Float64
+ * only (opts->prec must be NYS_FP64; no refinement is involved).  W is p x (nlam
+ * nrhs) (device), info and lambdas HOST, as nyspcg_solve; check_true reports the
+ * float64 residual |(X^T X + lambda I) w - X^T y| / |X^T y| (eq.
+ * experiment-relative-residual).  Returns NYS_OK or NYS_NOT_CONVERGED. */
+int32_t nys_ridge_sketch(const double *X, int64_t n, int64_t p, const double *Omega, uint64_t seed, int32_t r,
+                         double *Q, double *Y, void *ws, size_t ws_bytes, void *stream);
+int32_t nys_ridge_solve(const double *X, int64_t n, int64_t p, const double *Yt, int32_t nrhs,
+                        const double *lambdas, int32_t nlam, const nys_precond *P, const nys_pcg_opts *opts,
+                        double *W, nys_col_info *info, void *ws, size_t ws_bytes, void *stream);
 
 /* Thread-local description of the last non-zero status ("" if none). */
 const char *nys_last_error(void);

@@ -169,3 +169,149 @@ WORKLOADS = {
     "differentiation": differentiation,
     "batched_lambda_grid": batched_lambda_grid,
 }
+
+
+# ----------------------------------------------------------------------------- ridge regression
+
+def fwht(A: np.ndarray) -> np.ndarray:
+    """Unnormalised fast Walsh-Hadamard transform of the columns of A (axis 0 of
+    length 2^k): H A with H_ij = (-1)^popcount(i & j)."""
+    A = np.array(A, dtype=np.float64)
+    n = A.shape[0]
+    if n & (n - 1):
+        raise ValueError("length must be a power of two")
+    rest = A.shape[1:]
+    h = 1
+    while h < n:
+        B = A.reshape((n // (2 * h), 2, h) + rest)
+        a, b = B[:, 0].copy(), B[:, 1].copy()
+        B[:, 0], B[:, 1] = a + b, a - b
+        A = B.reshape((n,) + rest)
+        h *= 2
+    return A
+
+
+def sorf_columns(n: int, r: int, signs: np.ndarray) -> np.ndarray:
+    """The first r columns of the n x n orthogonal matrix H D1 H D2 H D3 (H the
+    normalised Walsh-Hadamard matrix, D_i = diag(signs[i]) with +-1 entries): the SORF
+    construction of Yu et al. (2016), the generator the paper names for the ridge
+    data's orthonormal factors."""
+    M = np.zeros((n, r))
+    M[np.arange(r), np.arange(r)] = signs[2][:r]
+    s = 1.0 / math.sqrt(n)
+    M = fwht(M) * s
+    M *= signs[1][:, None]
+    M = fwht(M) * s
+    M *= signs[0][:, None]
+    return fwht(M) * s
+
+
+@dataclass
+class RidgeProblem:
+    """Ridge regression data of eq. experiment-ridge-data: X = U Sigma_alpha V^T with
+    Sigma_alpha = diag(i^(-alpha/2)), i = 1..min(n, p), and y = U g / |g|."""
+    X: np.ndarray
+    y: np.ndarray
+    U: np.ndarray
+    V: np.ndarray
+    sigma: np.ndarray
+    alpha: float
+    seed: int
+
+
+def ridge_problem(n: int, p: int, alpha: float, seed: int = 0) -> RidgeProblem:
+    """n >= p, both powers of two; U (n x r) and V (p x r), r = min(n, p), are the first
+    columns of independent SORF matrices, g ~ N(0, I_r)."""
+    if n < p:
+        raise ValueError("the paper's ridge problems have n >= p")
+    rng = np.random.default_rng(seed)
+    r = min(n, p)
+    su = rng.choice(np.array([-1.0, 1.0]), size=(3, n))
+    sv = rng.choice(np.array([-1.0, 1.0]), size=(3, p))
+    g = rng.standard_normal(r)
+    U = sorf_columns(n, r, su)
+    V = sorf_columns(p, r, sv)
+    sig = np.arange(1, r + 1, dtype=np.float64) ** (-alpha / 2.0)
+    X = (U * sig) @ V.T
+    y = U @ (g / np.linalg.norm(g))
+    return RidgeProblem(np.ascontiguousarray(X), y, U, V, sig, alpha, seed)
+
+
+def ridge_problem_device(n: int, p: int, alpha: float, seed: int, device):
+    """ridge_problem's X and y built on a GPU with torch in float64 (the paper's sizes,
+    n = p = 2^16, are beyond host generation): the same sign and g draws from the same
+    numpy generator, the same Walsh-Hadamard stages and the same product, so the result
+    equals the host version up to rounding order.  Returns (X, y) as device tensors."""
+    import torch
+
+    if n < p:
+        raise ValueError("the paper's ridge problems have n >= p")
+    rng = np.random.default_rng(seed)
+    r = min(n, p)
+    su = rng.choice(np.array([-1.0, 1.0]), size=(3, n))
+    sv = rng.choice(np.array([-1.0, 1.0]), size=(3, p))
+    g = rng.standard_normal(r)
+
+    def fwht_(A):
+        m = A.shape[0]
+        h = 1
+        while h < m:
+            B = A.view(m // (2 * h), 2, h, A.shape[1])
+            a = B[:, 0].clone()
+            B[:, 0].add_(B[:, 1])
+            B[:, 1].neg_().add_(a)
+            del a
+            h *= 2
+        return A
+
+    def sorf(m, signs):
+        M = torch.zeros((m, r), dtype=torch.float64, device=device)
+        M[torch.arange(r, device=device), torch.arange(r, device=device)] = torch.from_numpy(signs[2][:r]).to(device)
+        s = 1.0 / math.sqrt(m)
+        fwht_(M).mul_(s)
+        M.mul_(torch.from_numpy(signs[1]).to(device)[:, None])
+        fwht_(M).mul_(s)
+        M.mul_(torch.from_numpy(signs[0]).to(device)[:, None])
+        return fwht_(M).mul_(s)
+
+    gt = torch.from_numpy(g / np.linalg.norm(g)).to(device)
+    U = sorf(n, su)
+    y = U @ gt
+    U.mul_(torch.arange(1, r + 1, dtype=torch.float64, device=device).pow_(-alpha / 2.0))
+    V = sorf(p, sv)
+    X = U @ V.T
+    del U, V
+    return X.contiguous(), y
+
+
+# ----------------------------------------------------------------------------- bounded elastic net
+
+@dataclass
+class ElasticNetProblem:
+    """Bounded elastic net data (eq. experiment-bounded-en): dense random-feature
+    matrix X (n x p), centred and scaled target y, lam1 = lam2 = 0.1 lam_max with
+    lam_max = |X^T (y - ybar)|_inf / n."""
+    X: np.ndarray
+    y: np.ndarray
+    lam1: float
+    lam2: float
+    seed: int
+
+
+def elastic_net_problem(n: int, d_in: int, p: int, seed: int = 0) -> ElasticNetProblem:
+    """Synthetic stand-in for the paper's dense random-feature problems (its data
+    table: standardised inputs, Gaussian random features): inputs Z (n x d_in)
+    column-standardised N(0, 1); features X = sqrt(2/p) cos(Z W / sqrt(d_in) + c)
+    with W ~ N(0, 1), c ~ U[0, 2 pi) (random Fourier features of a Gaussian kernel of
+    unit bandwidth in the scaled inputs); target t = tanh(Z v) + 0.1 N(0, 1), v ~
+    N(0, I/d_in), centred and divided by its standard deviation."""
+    rng = np.random.default_rng(seed)
+    Z = standardised_gaussian(rng, n, d_in)
+    W = rng.standard_normal((d_in, p))
+    c = rng.uniform(0.0, 2.0 * math.pi, size=p)
+    X = math.sqrt(2.0 / p) * np.cos(Z @ W / math.sqrt(d_in) + c)
+    v = rng.standard_normal(d_in) / math.sqrt(d_in)
+    t = np.tanh(Z @ v) + 0.1 * rng.standard_normal(n)
+    y = (t - t.mean()) / t.std()
+    lam_max = float(np.max(np.abs(X.T @ (y - y.mean())))) / n
+    return ElasticNetProblem(np.ascontiguousarray(X), y, 0.1 * lam_max, 0.1 * lam_max, seed)

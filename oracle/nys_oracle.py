@@ -398,3 +398,153 @@ def unrolled_validation_grad(X, y, Xv, yv, kind, sigma, lam, U, lam_hat, iters: 
     L = (res @ res) / res.shape[0]
     L.backward()
     return float(L.detach()), float(lam_t.grad), float(sig_t.grad)
+
+
+# ---------------------------------------------------------------------------
+# Ridge regression (section "Large-Scale Ridge Regression with NysPCG")
+# ---------------------------------------------------------------------------
+
+def ridge_normal_apply(X):
+    """The normal matrix of eq. experiment-ridge as an operator, V -> X^T (X V), never
+    forming X^T X (for nystrom and pcg)."""
+    X = np.asarray(X, dtype=np.float64)
+    return lambda V: X.T @ (X @ V)
+
+
+def ridge_direct(X, y, lam):
+    """w* = (X^T X + lam I)^{-1} X^T y by Cholesky of the formed normal matrix."""
+    X = np.asarray(X, dtype=np.float64)
+    A = X.T @ X + lam * np.eye(X.shape[1])
+    c = sla.cho_factor(A, lower=True)
+    return sla.cho_solve(c, X.T @ np.asarray(y, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+# NysADMM on the bounded elastic net (sections "Splitting for ADMM" and
+# "Bounded Elastic Net with NysADMM"; tables tab:rlaopt-admm-config and
+# tab:rlaopt-admm-stopping)
+# ---------------------------------------------------------------------------
+
+def elastic_net_objective(X, y, w, b, lam1, lam2):
+    """(1/2n)|X w + b 1 - y|^2 + lam1 |w|_1 + lam2/2 |w|^2 (eq. experiment-bounded-en)."""
+    X = np.asarray(X, dtype=np.float64)
+    res = X @ w + b - np.asarray(y, dtype=np.float64)
+    return float(res @ res) / (2 * X.shape[0]) + lam1 * float(np.abs(w).sum()) + 0.5 * lam2 * float(w @ w)
+
+
+def elastic_net_prox(v, rho, lam1, lam2, lo, hi):
+    """Proximal map of g(z) = lam1 |z|_1 + lam2/2 |z|^2 + indicator(lo <= z <= hi) with
+    step 1/rho, coordinate by coordinate: the minimiser of lam1|z| + lam2/2 z^2 +
+    rho/2 (z - v)^2 over the real line is soft(v, lam1/rho) rho/(rho + lam2), and for a
+    convex function of one variable the minimiser over [lo, hi] is that point clipped."""
+    v = np.asarray(v, dtype=np.float64)
+    soft = np.sign(v) * np.maximum(np.abs(v) - lam1 / rho, 0.0)
+    return np.clip(soft * (rho / (rho + lam2)), lo, hi)
+
+
+def admm_subproblem_tol(k, gamma, r_pri_prev=None, r_dual_prev=None):
+    """Relative-residual tolerance of the k-th x-subproblem solve (k = 1, 2, ...):
+    min(1, sqrt(|r_pri| |r_dual|)) k^-gamma with the previous iteration's residual
+    norms (1 at k = 1): the inexact solve tracks the ADMM residuals and the factor
+    k^-gamma is summable for gamma > 1 (the decay exponent of table
+    tab:rlaopt-admm-config; the paper names the exponent and the adaptive tolerance of
+    the method it follows, and this is the reading of how they combine)."""
+    scale = 1.0 if r_pri_prev is None else min(1.0, math.sqrt(r_pri_prev * r_dual_prev))
+    return max(scale * float(k) ** (-gamma), 1e-15)
+
+
+def nysadmm_elastic_net(X, y, lam1, lam2, lo=0.0, hi=1.0, rho=1.0, rho_update_factor=2.0,
+                        rho_update_threshold=10.0, rho_update_freq=25, alpha=1.6, sigma=1e-6, gamma=1.2,
+                        rank=50, precond_update_freq=20, max_iters=1000, eps_abs=1e-4, eps_rel=1e-4,
+                        seed=0, pcg_max_iters=1000):
+    """NysADMM for the bounded elastic net with an unregularised intercept.
+
+    The intercept is eliminated by centring (X_c = X - 1 mu^T, y_c = y - ybar; at any w
+    the best intercept is ybar - mu^T w).  Splitting x = z with
+    f(x) = (1/2n)|X_c x - y_c|^2 and g the elastic-net penalty plus the box, each
+    iteration k = 1, 2, ... does, with the scaled dual u:
+      1. every precond_update_freq iterations, a fresh Nystrom approximation of the
+         Hessian H = X_c^T X_c / n from the test matrix Philox(seed + refresh count);
+      2. x-subproblem (H + (rho + sigma) I) x = X_c^T y_c / n + rho (z - u) + sigma x_prev
+         by NysPCG warm-started at x_prev, to relative residual admm_subproblem_tol
+         (preconditioner P = H_hat + (rho + sigma) I);
+      3. over-relaxation xh = alpha x + (1 - alpha) z;
+      4. z = elastic_net_prox(xh + u, rho, ...);  5. u = u + xh - z;
+      6. residuals r_pri = x - z and r_dual = grad f(x) + rho u, stop when both meet
+         the tolerances of table tab:rlaopt-admm-stopping (m = p constraints);
+      7. every rho_update_freq iterations, residual balancing: rho times (divided by)
+         the factor when |r_pri| exceeds (falls below 1/threshold of) |r_dual|, u
+         rescaled to keep rho u.
+    Returns a dict with w = z (feasible), b, iterations, convergence flag, the final
+    residual norms and rho, and the PCG iteration count of every subproblem."""
+    from . import philox
+
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n, p = X.shape
+    mu = X.mean(axis=0)
+    ybar = float(y.mean())
+    Xc = X - mu
+    yc = y - ybar
+    H = lambda V: Xc.T @ (Xc @ V) / n
+    c = Xc.T @ yc / n
+    x = np.zeros(p)
+    z = np.zeros(p)
+    u = np.zeros(p)
+    pcg_iters = []
+    converged = False
+    rp = rd = float("nan")
+    k = 0
+    for k in range(1, max_iters + 1):
+        if (k - 1) % precond_update_freq == 0:
+            Om = philox.gaussian_test_matrix(p, rank, seed + (k - 1) // precond_update_freq)
+            Uh, lh, _ = nystrom(H, Om)
+        lk = rho + sigma
+        rhs = c + rho * (z - u) + sigma * x
+        tol_k = admm_subproblem_tol(k, gamma, None if k == 1 else rp, None if k == 1 else rd)
+        x, it, _ = pcg(lambda v: H(v) + lk * v, rhs, lambda r: precond_apply(Uh, lh, lk, r),
+                       tol=tol_k, max_iters=pcg_max_iters, x0=x)
+        pcg_iters.append(it)
+        xh = alpha * x + (1.0 - alpha) * z
+        z = elastic_net_prox(xh + u, rho, lam1, lam2, lo, hi)
+        u = u + xh - z
+        rp = float(np.linalg.norm(x - z))
+        rd = float(np.linalg.norm(H(x) - c + rho * u))
+        eps_pri = math.sqrt(p) * eps_abs + eps_rel * max(float(np.linalg.norm(x)), float(np.linalg.norm(z)))
+        eps_dual = math.sqrt(p) * eps_abs + eps_rel * float(np.linalg.norm(rho * u))
+        if rp <= eps_pri and rd <= eps_dual:
+            converged = True
+            break
+        if k % rho_update_freq == 0:
+            if rp > rho_update_threshold * rd:
+                rho *= rho_update_factor
+                u /= rho_update_factor
+            elif rd > rho_update_threshold * rp:
+                rho /= rho_update_factor
+                u *= rho_update_factor
+    return {"w": z, "b": ybar - float(mu @ z), "iters": k, "converged": converged, "r_pri": rp, "r_dual": rd,
+            "rho": rho, "pcg_iters": pcg_iters}
+
+
+def elastic_net_kkt(X, y, w, lam1, lam2, lo=0.0, hi=1.0):
+    """Stationarity violation of a bounded elastic-net point w (intercept at its optimum):
+    the distance from -grad of the smooth part to the subdifferential of
+    lam1 |.|_1 + box at w, coordinate by coordinate, as an infinity norm."""
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = X.shape[0]
+    mu = X.mean(axis=0)
+    Xc = X - mu
+    gsm = Xc.T @ (Xc @ w - (y - y.mean())) / n + lam2 * w
+    viol = np.empty_like(w)
+    for i, wi in enumerate(w):
+        # subdifferential of lam1|t| at wi, plus the normal cone of [lo, hi]
+        lo_s = lam1 * (np.sign(wi) if wi != 0 else -1.0)
+        hi_s = lam1 * (np.sign(wi) if wi != 0 else 1.0)
+        if wi <= lo:
+            lo_s = -np.inf
+        if wi >= hi:
+            hi_s = np.inf
+        t = -gsm[i]
+        viol[i] = 0.0 if lo_s <= t <= hi_s else min(abs(t - lo_s), abs(t - hi_s))
+    return float(np.max(np.abs(viol))) if w.size else 0.0

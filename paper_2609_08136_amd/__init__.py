@@ -25,12 +25,13 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 (OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BACKWARD, OP_AUTOTUNE,
- OP_KERNEL_DOT, OP_PRECOND_ADAPTIVE) = range(9)
+ OP_KERNEL_DOT, OP_PRECOND_ADAPTIVE, OP_RIDGE_SKETCH, OP_RIDGE_SOLVE) = range(11)
 
 EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "kernel_dot", "nys_test_matrix", "nys_sketch", "nys_precond_build",
            "nys_precond_adaptive",
            "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_autotune", "nys_set_tile",
-           "nys_clear_tiles", "nys_plan_chunks", "nys_peak_probe", "nys_last_error", "nys_version")
+           "nys_clear_tiles", "nys_plan_chunks", "nys_peak_probe", "nys_ridge_sketch", "nys_ridge_solve",
+           "nys_last_error", "nys_version")
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -55,7 +56,7 @@ class NysNystromConfig(ctypes.Structure):
 class NysPCGOpts(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("max_iters", c_i32), ("prec", c_i32), ("refine_every", c_i32),
                 ("refine_mode", c_i32), ("check_true", c_i32), ("max_refinements", c_i32),
-                ("refine_reduction", c_f64)]
+                ("refine_reduction", c_f64), ("refine_join", c_f64)]
 
 
 class NysColInfo(ctypes.Structure):
@@ -114,6 +115,10 @@ def load(path: str | None = None):
     lib.nys_clear_tiles.restype = None
     lib.nys_plan_chunks.argtypes = [c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
     lib.nys_peak_probe.argtypes = [c_i32, c_i32, ctypes.POINTER(c_f64), c_vp, c_sz, c_vp]
+    lib.nys_ridge_sketch.argtypes = [c_vp, c_i64, c_i64, c_vp, ctypes.c_uint64, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]
+    lib.nys_ridge_solve.argtypes = [c_vp, c_i64, c_i64, c_vp, c_i32, ctypes.POINTER(c_f64), c_i32,
+                                    ctypes.POINTER(NysPrecondC), ctypes.POINTER(NysPCGOpts), c_vp,
+                                    ctypes.POINTER(NysColInfo), c_vp, c_sz, c_vp]
     for name in ("kernel_matvec", "kernel_dot", "nys_test_matrix", "nys_sketch", "nys_precond_adaptive", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
                  "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile", "nys_plan_chunks",
                  "nys_peak_probe"):
@@ -358,9 +363,9 @@ def nys_precond_apply(P: Preconditioner, lambdas, R, prec: int = FP64):
 
 
 def _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements,
-          refine_reduction=1e-3) -> NysPCGOpts:
+          refine_reduction=1e-3, refine_join=0.0) -> NysPCGOpts:
     return NysPCGOpts(float(tol), int(max_iters), int(prec), int(refine_every), int(refine_mode), int(check_true),
-                      int(max_refinements), float(refine_reduction))
+                      int(max_refinements), float(refine_reduction), float(refine_join))
 
 
 def _info_list(arr, count):
@@ -371,7 +376,7 @@ def _info_list(arr, count):
 def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | None = None, tol: float = 1e-6,
                  max_iters: int = 1000, prec: int = FP64, refine_every: int = -1, refine_mode: int = 0,
                  check_true: bool = False, max_refinements: int = 0, workspace: torch.Tensor | None = None,
-                 refine_reduction: float = 1e-3):
+                 refine_reduction: float = 1e-3, refine_join: float = 0.0):
     """Solve (K + lambdas[l] I) x = B[:, j] for every (l, j); column l*nrhs + j of the result.
     Returns (Xsol (n x nlam*nrhs float64), info list, status)."""
     lib = load()
@@ -389,7 +394,8 @@ def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | Non
     lam_arr = (c_f64 * nlam)(*lams)
     need = nys_workspace_bytes(OP_SOLVE, n, 0, d, P.r if P is not None else 0, m, prec)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
-    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements, refine_reduction)
+    o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements, refine_reduction,
+              refine_join)
     cs = P.c_struct() if P is not None else None
     rc = lib.nyspcg_solve(NysKernel(kind, 0, float(sigma)), X.data_ptr(), n, d, B2.data_ptr(), nrhs, lam_arr, nlam,
                           ctypes.byref(cs) if cs is not None else None, ctypes.byref(o), Xsol.data_ptr(), info,
@@ -432,6 +438,59 @@ def build_preconditioner(X, Omega, kind: int, sigma: float, sketch_prec: int = F
     P = nys_precond_build(Y, Q, sketch_prec, with_fp32)
     del Y, Q
     return P
+
+
+# ------------------------------------------------------------------------------ ridge regression
+
+def nys_ridge_sketch(X, Omega, seed: int = 0, r: int | None = None):
+    """(Y, Q) of the Nystrom sketch of the normal matrix X^T X (X: n x p float64 CUDA):
+    Q the orthonormalised p x r test matrix, Y = X^T (X Q).  Omega as nys_sketch."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    n, p = X.shape
+    if Omega is not None:
+        _need_cuda(Omega, torch.float64, "Omega")
+        if Omega.shape[0] != p or (r is not None and Omega.shape[1] != r):
+            raise ValueError("Omega must be p x r")
+        r = Omega.shape[1]
+    elif r is None:
+        raise ValueError("r is required when Omega is None")
+    Y = torch.empty((p, r), dtype=torch.float64, device=X.device)
+    Q = torch.empty((p, r), dtype=torch.float64, device=X.device)
+    ws = _workspace(nys_workspace_bytes(OP_RIDGE_SKETCH, n, p, 0, r), X.device)
+    rc = lib.nys_ridge_sketch(X.data_ptr(), n, p, Omega.data_ptr() if Omega is not None else None,
+                              int(seed) & 0xFFFFFFFFFFFFFFFF, r, Q.data_ptr(), Y.data_ptr(), ws.data_ptr(),
+                              ws.numel(), _stream())
+    _check(rc, allow_not_converged=False)
+    return Y, Q
+
+
+def nys_ridge_solve(X, Y, lambdas, P: Preconditioner | None = None, tol: float = 1e-10, max_iters: int = 1000,
+                    check_true: bool = False):
+    """NysPCG (CG when P is None) on (X^T X + lambda I) w = X^T y for every lambda and
+    every column of Y (n x nrhs, or a vector); column l*nrhs + j of the result.
+    Returns (W (p x nlam*nrhs float64), info list, status)."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    vec = Y.dim() == 1
+    Y2 = Y.reshape(-1, 1) if vec else Y
+    _need_cuda(Y2, torch.float64, "Y")
+    n, p = X.shape
+    nrhs = Y2.shape[1]
+    lams = [float(v) for v in (lambdas if hasattr(lambdas, "__len__") else [lambdas])]
+    nlam = len(lams)
+    m = nlam * nrhs
+    W = torch.empty((p, m), dtype=torch.float64, device=X.device)
+    info = (NysColInfo * m)()
+    lam_arr = (c_f64 * nlam)(*lams)
+    ws = _workspace(nys_workspace_bytes(OP_RIDGE_SOLVE, n, p, nrhs, P.r if P is not None else 0, m), X.device)
+    o = _opts(tol, max_iters, FP64, 0, 0, check_true, 0)
+    cs = P.c_struct() if P is not None else None
+    rc = lib.nys_ridge_solve(X.data_ptr(), n, p, Y2.data_ptr(), nrhs, lam_arr, nlam,
+                             ctypes.byref(cs) if cs is not None else None, ctypes.byref(o), W.data_ptr(), info,
+                             ws.data_ptr(), ws.numel(), _stream())
+    _check(rc)
+    return (W.reshape(-1) if (vec and nlam == 1) else W), _info_list(info, m), rc
 
 
 # ------------------------------------------------------------------------------ autotuner

@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
+
+#include <rocblas/rocblas.h>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -266,12 +269,14 @@ struct SolvePlan {
 };
 
 void plan_solve(SolvePlan &p, int64_t n, int d, int r, int m, int prec, bool refine, bool check_true,
-                Arena &ws) {
+                Arena &ws, bool kernel = true) {
   p.prec = prec;
   p.lowp = prec != NYS_FP64;
   p.need64 = p.lowp && (refine || check_true);
-  plan_kmv(p.kv, n, n, d, 1, m, prec, ws);
-  if (p.need64) plan_kmv(p.kv64, n, n, d, 1, m, NYS_FP64, ws);
+  if (kernel) {
+    plan_kmv(p.kv, n, n, d, 1, m, prec, ws);
+    if (p.need64) plan_kmv(p.kv64, n, n, d, 1, m, NYS_FP64, ws);
+  }
   const size_t vb = (size_t)n * m * elem_bytes(prec);
   p.X = ws.take<char>(vb);
   p.R = ws.take<char>(vb);
@@ -342,6 +347,122 @@ int32_t apply_precond_or_copy(const nys_precond *P, SolvePlan &sp, const T *R, i
   a.base = sp.pws;
   a.cap = sp.pws_bytes;
   return precond_apply_impl<T>(*P, sp.lam, R, m, Z, a, s);
+}
+
+// The kernel matrix as the solver's operator: products at the solve's precision and,
+// for refinement, in float64 (its own packing when the solve runs in low precision).
+struct KernelOp {
+  const nys_kernel &k;
+  const double *X;
+  int d;
+  SolvePlan &sp;
+  int32_t prepare(hipStream_t s) {
+    NYS_RETURN_IF(prep_points(sp.kv, k, sp.prec, X, X, d, s));
+    if (sp.need64) NYS_RETURN_IF(prep_points(sp.kv64, k, NYS_FP64, X, X, d, s));
+    return NYS_OK;
+  }
+  int32_t apply(const void *V, int m, int ldv, void *Out, int ldo, hipStream_t s) {
+    return run_kmv(sp.kv, k, 0, sp.prec, 1, V, m, ldv, Out, ldo, 1.0, 0.0, s);
+  }
+  int32_t apply64(const double *V, int m, int ldv, double *Out, int ldo, hipStream_t s) {
+    return run_kmv(sp.need64 ? sp.kv64 : sp.kv, k, 0, NYS_FP64, 1, V, m, ldv, Out, ldo, 1.0, 0.0, s);
+  }
+};
+
+// ------------------------------------------------------------ ridge normal operator
+// One rocBLAS handle per device, created on first use (plain library GEMMs).
+int32_t blas_handle(rocblas_handle *out) {
+  static std::mutex mu;
+  static std::vector<rocblas_handle> handles;
+  int dev = 0;
+  NYS_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)handles.size() <= dev) handles.resize(dev + 1, nullptr);
+  if (!handles[dev]) {
+    rocblas_handle h = nullptr;
+    // atomics off: the same call gives the same bits, as every other product here
+    if (rocblas_create_handle(&h) != rocblas_status_success ||
+        rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success) {
+      if (h) rocblas_destroy_handle(h);
+      set_error("rocBLAS handle creation failed");
+      return NYS_EHIP;
+    }
+    handles[dev] = h;
+  }
+  *out = handles[dev];
+  return NYS_OK;
+}
+
+// The normal matrix X^T X of ridge regression (eq. experiment-ridge) on p-vectors,
+// applied matrix-free as two products with the dense n x p data matrix X (row-major),
+// never forming X^T X: T = X V (n x m), K V = X^T T, both float64 GEMMs.  In rocBLAS's
+// column-major terms a row-major a x b matrix is its b x a transpose.
+struct RidgeOp {
+  const double *X;
+  int64_t nrows, p;
+  double *T;            // nrows x m scratch
+  rocblas_handle h = nullptr;
+  int32_t prepare(hipStream_t s) {
+    NYS_RETURN_IF(blas_handle(&h));
+    if (rocblas_set_stream(h, s) != rocblas_status_success) {
+      set_error("rocblas_set_stream failed");
+      return NYS_EHIP;
+    }
+    return NYS_OK;
+  }
+  int32_t apply(const void *V, int m, int ldv, void *Out, int ldo, hipStream_t s) {
+    return apply64(reinterpret_cast<const double *>(V), m, ldv, reinterpret_cast<double *>(Out), ldo, s);
+  }
+  int32_t apply64(const double *V, int m, int ldv, double *Out, int ldo, hipStream_t s) {
+    if (m <= 0) return NYS_OK;
+    NYS_RETURN_IF(prepare(s));
+    const double one = 1.0, zero = 0.0;
+    if (m == 1) {
+      // one column: two matrix-vector products, each a single pass over X
+      if (rocblas_dgemv_64(h, rocblas_operation_transpose, (int64_t)p, (int64_t)nrows, &one, X, (int64_t)p,
+                        V, ldv, &zero, T, 1) != rocblas_status_success ||
+          rocblas_dgemv_64(h, rocblas_operation_none, (int64_t)p, (int64_t)nrows, &one, X, (int64_t)p, T, 1,
+                        &zero, Out, ldo) != rocblas_status_success) {
+        set_error("rocblas_dgemv failed in the ridge operator");
+        return NYS_EHIP;
+      }
+      return NYS_OK;
+    }
+    if (rocblas_dgemm_64(h, rocblas_operation_none, rocblas_operation_none, m, (int64_t)nrows, (int64_t)p, &one,
+                      V, ldv, X, (int64_t)p, &zero, T, m) != rocblas_status_success ||
+        rocblas_dgemm_64(h, rocblas_operation_none, rocblas_operation_transpose, m, (int64_t)p, (int64_t)nrows,
+                      &one, T, m, X, (int64_t)p, &zero, Out, ldo) != rocblas_status_success) {
+      set_error("rocblas_dgemm failed in the ridge operator");
+      return NYS_EHIP;
+    }
+    return NYS_OK;
+  }
+};
+
+// Scratch of the ridge calls: the normal-operator intermediate (n x m) and, for the
+// solve, the right-hand sides X^T y (p x nrhs); for the sketch, the Cholesky QR.
+struct RidgeSketchPlan {
+  double *G = nullptr, *Gpart = nullptr, *Linv = nullptr, *LinvT = nullptr, *Om = nullptr, *T = nullptr;
+  int *flag = nullptr;
+};
+void plan_ridge_sketch(RidgeSketchPlan &p, int64_t n, int64_t pd, int r, Arena &ws) {
+  const int splits = gemm_tn_splits(pd, r, r);
+  p.G = ws.take<double>((size_t)r * r);
+  p.Gpart = ws.take<double>((size_t)splits * r * r);
+  p.Linv = ws.take<double>((size_t)r * r);
+  p.LinvT = ws.take<double>((size_t)r * r);
+  p.Om = ws.take<double>((size_t)pd * r);
+  p.T = ws.take<double>((size_t)n * r);
+  p.flag = ws.take<int>(4);
+}
+struct RidgeSolvePlan {
+  SolvePlan sp;
+  double *T = nullptr, *B = nullptr;
+};
+void plan_ridge_solve(RidgeSolvePlan &p, int64_t n, int64_t pd, int r, int nrhs, int m, Arena &ws) {
+  plan_solve(p.sp, pd, 1, r, m, NYS_FP64, false, true, ws, false);
+  p.T = ws.take<double>((size_t)n * m);
+  p.B = ws.take<double>((size_t)pd * nrhs);
 }
 
 // The PCG driver (solve_columns).
@@ -571,6 +692,8 @@ int32_t check_opts(const nys_pcg_opts *o) {
   if (o->max_iters < 0) return einval("max_iters must be >= 0");
   if (!valid_prec(o->prec)) return einval("unsupported precision");
   if (o->refine_mode < 0 || o->refine_mode > 2) return einval("refine_mode must be 0, 1 or 2");
+  if (!(o->refine_join == 0.0 || o->refine_join >= 1.0) || !std::isfinite(o->refine_join))
+    return einval("refine_join must be 0 or >= 1");
   return NYS_OK;
 }
 
@@ -626,6 +749,16 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
     case NYS_OP_PRECOND_ADAPTIVE: {
       AdaptPlan p;
       plan_adapt(p, std::max<int64_t>(n, 1), std::max(d, 1), std::max(r, 1), prec, a);
+      break;
+    }
+    case NYS_OP_RIDGE_SKETCH: {
+      RidgeSketchPlan p;
+      plan_ridge_sketch(p, std::max<int64_t>(n, 1), std::max<int64_t>(n2, 1), std::max(r, 1), a);
+      break;
+    }
+    case NYS_OP_RIDGE_SOLVE: {
+      RidgeSolvePlan p;
+      plan_ridge_solve(p, std::max<int64_t>(n, 1), std::max<int64_t>(n2, 1), r, std::max(d, 1), std::max(m, 1), a);
       break;
     }
     case NYS_OP_KERNEL_DOT: {
@@ -920,9 +1053,80 @@ int32_t nyspcg_solve(nys_kernel k, const double *X, int64_t n, int32_t d, const 
   SolvePlan sp;
   plan_solve(sp, n, d, P ? P->r : 0, m, prec, opts->refine_every >= 0, opts->check_true != 0, a);
   NYS_RETURN_IF(check_ws(a));
+  KernelOp op{k, X, d, sp};
   if (prec == NYS_FP64)
-    return solve_columns<double>(k, X, n, d, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, s);
-  return solve_columns<float>(k, X, n, d, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, s);
+    return solve_columns<double>(op, n, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, s);
+  return solve_columns<float>(op, n, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, s);
+}
+
+int32_t nys_ridge_sketch(const double *X, int64_t n, int64_t p, const double *Omega, uint64_t seed, int32_t r,
+                         double *Q, double *Y, void *ws, size_t ws_bytes, void *stream) {
+  if (n < 1 || p < 1 || n > INT32_MAX || p > INT32_MAX) return einval("need 1 <= n, p < 2^31");
+  if (r < 1 || r > p || r > 1024) return einval("need 1 <= r <= min(p, 1024)");
+  if (!X || !Q || !Y || !ws) return einval("null pointer");
+  const int64_t cnt = p * (int64_t)r;
+  if (Omega && Omega + cnt > Q && Q + cnt > Omega) return einval("Q must not overlap Omega");
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  RidgeSketchPlan pl;
+  plan_ridge_sketch(pl, n, p, r, a);
+  NYS_RETURN_IF(check_ws(a));
+  const double *Om = Omega;
+  if (!Om) {
+    NYS_RETURN_IF(launch_gaussian(seed, cnt, pl.Om, s));
+    Om = pl.Om;
+  }
+  const int splits = gemm_tn_splits(p, r, r);
+  NYS_RETURN_IF(gemm_tn<double>(Om, r, Om, r, p, r, r, pl.G, r, pl.Gpart, splits, s));
+  NYS_RETURN_IF(launch_chol(pl.G, r, pl.flag, s));
+  int flag = 0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&flag, pl.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    set_error("nys_ridge_sketch: the test matrix Omega is rank deficient or not finite");
+    return NYS_ENOTPD;
+  }
+  NYS_RETURN_IF(launch_trinv_lower(pl.G, pl.Linv, r, s));
+  NYS_RETURN_IF(launch_transpose(pl.Linv, pl.LinvT, r, s));
+  NYS_RETURN_IF(gemm_nn<double>(Om, r, pl.LinvT, r, p, r, r, Q, r, 0, nullptr, 0, nullptr, s));
+  RidgeOp op{X, n, p, pl.T};
+  NYS_RETURN_IF(op.apply64(Q, r, r, Y, r, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  return NYS_OK;
+}
+
+int32_t nys_ridge_solve(const double *X, int64_t n, int64_t p, const double *Yt, int32_t nrhs,
+                        const double *lambdas, int32_t nlam, const nys_precond *P, const nys_pcg_opts *opts,
+                        double *W, nys_col_info *info, void *ws, size_t ws_bytes, void *stream) {
+  NYS_RETURN_IF(check_opts(opts));
+  if (opts->prec != NYS_FP64) return einval("the ridge solve runs in float64 (prec NYS_FP64)");
+  if (n < 1 || p < 1 || n > INT32_MAX || p > INT32_MAX) return einval("need 1 <= n, p < 2^31");
+  if (nrhs < 1 || nlam < 1) return einval("nrhs and nlam must be >= 1");
+  if ((int64_t)nrhs * nlam > 4096) return einval("at most 4096 columns per solve");
+  if (!X || !Yt || !lambdas || !W || !info || !ws) return einval("null pointer");
+  for (int l = 0; l < nlam; ++l)
+    if (!(lambdas[l] > 0.0) || !std::isfinite(lambdas[l])) return einval("every lambda must be > 0 and finite");
+  NYS_RETURN_IF(check_precond(P, p, NYS_FP64));
+  hipStream_t s = as_stream(stream);
+  const int m = nrhs * nlam;
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  RidgeSolvePlan pl;
+  plan_ridge_solve(pl, n, p, P ? P->r : 0, nrhs, m, a);
+  NYS_RETURN_IF(check_ws(a));
+  RidgeOp op{X, n, p, pl.T};
+  NYS_RETURN_IF(op.prepare(s));
+  // right-hand sides X^T y (p x nrhs)
+  const double one = 1.0, zero = 0.0;
+  if (rocblas_dgemm_64(op.h, rocblas_operation_none, rocblas_operation_transpose, nrhs, (int64_t)p, (int64_t)n,
+                    &one, Yt, nrhs, X, (int64_t)p, &zero, pl.B, nrhs) != rocblas_status_success) {
+    set_error("rocblas_dgemm failed forming X^T y");
+    return NYS_EHIP;
+  }
+  return solve_columns<double>(op, p, pl.B, nrhs, lambdas, nlam, P, *opts, W, info, pl.sp, s);
 }
 
 int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, double lambda,
@@ -947,10 +1151,11 @@ int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, dou
   NYS_RETURN_IF(check_ws(a));
   // adjoint solve (K + lambda I) a = gx with the same preconditioner
   int32_t rc;
+  KernelOp op{k, X, d, sp};
   if (prec == NYS_FP64)
-    rc = solve_columns<double>(k, X, n, d, gx, 1, &lambda, 1, P, *opts, adj, info, sp, s);
+    rc = solve_columns<double>(op, n, gx, 1, &lambda, 1, P, *opts, adj, info, sp, s);
   else
-    rc = solve_columns<float>(k, X, n, d, gx, 1, &lambda, 1, P, *opts, adj, info, sp, s);
+    rc = solve_columns<float>(op, n, gx, 1, &lambda, 1, P, *opts, adj, info, sp, s);
   if (rc < 0) return rc;
   // dL/dlambda = -a^T x ;  dL/dsigma = -a^T (dK/dsigma) x
   NYS_RETURN_IF(prep_points(dp.kv, k, NYS_FP64, X, X, d, s));

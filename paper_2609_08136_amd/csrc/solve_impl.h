@@ -1,6 +1,7 @@
 // The PCG driver over a block of independent columns.  Included by api.hip
-// inside its anonymous namespace (uses SolvePlan, KmvBufs, run_kmv,
-// prep_points and apply_precond_or_copy defined there).
+// inside its anonymous namespace (uses SolvePlan and apply_precond_or_copy
+// defined there); the operator is a template argument (the kernel matrix, or the
+// ridge normal matrix).
 //
 // Columns are kept compacted: slot q < ma holds original column sl[q].orig;
 // finished columns are written to Xsol and removed, so the kernel product
@@ -32,8 +33,11 @@ struct Slot {
   int iters = 0, refs = 0, restart = 0;
 };
 
-template <class T>
-int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d, const double *B, int nrhs,
+// Op supplies the operator K of (K + lambda I) on n-vectors: prepare(s) once, then
+// apply(V, m, ldv, Out, ldo, s) (Out = K V in the solve's precision) and apply64
+// (the same in float64, for refinement residuals and the true-residual check).
+template <class T, class Op>
+int32_t solve_columns(Op &op, int64_t n, const double *B, int nrhs,
                       const double *lambdas, int nlam, const nys_precond *P, const nys_pcg_opts &o,
                       double *Xsol, nys_col_info *info, SolvePlan &sp, hipStream_t s) {
   const int mtot = nlam * nrhs;
@@ -41,6 +45,7 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
   const bool lowp = sp.lowp;
   const bool refine = lowp && o.refine_every >= 0;
   const int max_refs = o.max_refinements > 0 ? o.max_refinements : 50;
+  const double join = o.refine_join > 0.0 ? o.refine_join : 3.0;
   const double tol = o.tol;
   const double delta0 = o.refine_reduction > 0.0 ? std::min(o.refine_reduction, 0.5) : 0.0;
   const bool verbose = std::getenv("NYS_VERBOSE") != nullptr;
@@ -48,9 +53,7 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
   T *Pd = reinterpret_cast<T *>(sp.P), *W = reinterpret_cast<T *>(sp.W), *Sp = reinterpret_cast<T *>(sp.Spare);
   double *X64 = sp.X64, *R64 = sp.R64, *Sp64 = sp.Spare64;
 
-  NYS_RETURN_IF(prep_points(sp.kv, k, prec, Xpts, Xpts, d, s));
-  if (sp.need64) NYS_RETURN_IF(prep_points(sp.kv64, k, NYS_FP64, Xpts, Xpts, d, s));
-  KmvBufs &k64 = sp.need64 ? sp.kv64 : sp.kv;
+  NYS_RETURN_IF(op.prepare(s));
 
   std::vector<Slot> sl(mtot);
   std::vector<int> ih(mtot);
@@ -149,14 +152,14 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
       NYS_CHECK_HIP(hipMemcpyAsync(sp.bcol2, bs.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
       NYS_CHECK_HIP(hipMemcpyAsync(sp.lam2, ls.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
       NYS_RETURN_IF(gather_cols<double>(X64, ma, sp.idx, ns, Sp64, n, s));
-      NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, Sp64, ns, ns, R64, ns, 1.0, 0.0, s));
+      NYS_RETURN_IF(op.apply64(Sp64, ns, ns, R64, ns, s));
       NYS_RETURN_IF(residual64(B, nrhs, sp.bcol2, sp.lam2, Sp64, R64, nullptr, n, ns, s));
       if (drift) NYS_RETURN_IF(gapnorm<T>(R64, ns, R, ma, sp.idx, n, sp.red, s));
       if (drift) NYS_RETURN_IF(colfinal(sp.red, n, ns, 0, sp.tmpc, nullptr, nullptr, nullptr, nullptr, s));
       if (drift) NYS_CHECK_HIP(hipMemcpyAsync(gap_h.data(), sp.tmpc, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
       NYS_RETURN_IF(scatter_cols_d2f(R64, ns, sp.idx, reinterpret_cast<float *>(R), ma, n, s));
     } else {
-      NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, X64, ma, ma, R64, ma, 1.0, 0.0, s));
+      NYS_RETURN_IF(op.apply64(X64, ma, ma, R64, ma, s));
       NYS_RETURN_IF(residual64(B, nrhs, sp.bcol, sp.lam, X64, R64, drift ? nullptr : reinterpret_cast<float *>(R),
                                n, ma, s));
       if (drift) {
@@ -200,7 +203,7 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
   while (ma > 0 && iter < o.max_iters) {
     ++iter;
     // w = K p + lambda p ; alpha = rho / p^T w
-    NYS_RETURN_IF(run_kmv(sp.kv, k, 0, prec, 1, Pd, ma, ma, W, ma, 1.0, 0.0, s));
+    NYS_RETURN_IF(op.apply(Pd, ma, ma, W, ma, s));
     NYS_RETURN_IF(colred<T>(1, Pd, W, nullptr, nullptr, n, ma, sp.lam, sp.red, s));
     NYS_RETURN_IF(colfinal(sp.red, n, ma, 1, nullptr, sp.rho, sp.ab, nullptr, sp.flag, s));
     // x += alpha p ; r -= alpha w ; rr = r^T r   (low precision: x accumulated in float64)
@@ -262,7 +265,7 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
         if (stop[q]) continue;
         const bool capped = sl[q].iters >= o.max_iters;   // report its true residual before it stops
         const bool take = periodic || capped || dv[q] ? true
-                        : (o.refine_every > 0 ? rel[q] <= tol : (any_due && rel[q] <= 3.0 * thr[q]));
+                        : (o.refine_every > 0 ? rel[q] <= tol : (any_due && rel[q] <= join * thr[q]));
         if (take) sel.push_back(q);
       }
       if (!sel.empty()) {
@@ -354,7 +357,7 @@ int32_t solve_columns(const nys_kernel &k, const double *Xpts, int64_t n, int d,
   }
   // optional float64 true residual of every column
   if (o.check_true && R64) {
-    NYS_RETURN_IF(run_kmv(k64, k, 0, NYS_FP64, 1, Xsol, mtot, mtot, R64, mtot, 1.0, 0.0, s));
+    NYS_RETURN_IF(op.apply64(Xsol, mtot, mtot, R64, mtot, s));
     std::vector<int> bc(mtot);
     std::vector<double> lm(mtot);
     for (int c = 0; c < mtot; ++c) {

@@ -85,9 +85,9 @@ def test_kernel_matvec_argument_errors(lib):
 def test_solve_argument_errors(lib):
     k = nys.NysKernel(nys.RBF, 0, 1.0)
     info = (nys.NysColInfo * 4)()
-    def solve(lams, tol=1e-6, prec=0, mode=0, nrhs=1, max_iters=10):
+    def solve(lams, tol=1e-6, prec=0, mode=0, nrhs=1, max_iters=10, join=0.0):
         arr = (ctypes.c_double * len(lams))(*lams)
-        o = nys.NysPCGOpts(tol, max_iters, prec, -1, mode, 0, 0)
+        o = nys.NysPCGOpts(tol, max_iters, prec, -1, mode, 0, 0, 0.0, join)
         return lib.nyspcg_solve(k, FAKE, 10, 2, FAKE, nrhs, arr, len(lams), None, ctypes.byref(o), FAKE, info,
                                 FAKE, 1 << 30, None)
     assert solve([0.0]) == nys.EINVAL          # lambda must be > 0 (eq. rlaopt-regularized-linear-system)
@@ -96,6 +96,8 @@ def test_solve_argument_errors(lib):
     assert solve([1.0], tol=0.0) == nys.EINVAL
     assert solve([1.0], prec=6) == nys.EINVAL
     assert solve([1.0], mode=3) == nys.EINVAL
+    assert solve([1.0], join=0.5) == nys.EINVAL     # a join window below the due point
+    assert solve([1.0], join=float("inf")) == nys.EINVAL
     assert solve([1.0], max_iters=-1) == nys.EINVAL
     assert solve([1.0], nrhs=0) == nys.EINVAL
     assert b"lambda" in lib.nys_last_error() or b"nrhs" in lib.nys_last_error()

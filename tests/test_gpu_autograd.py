@@ -102,18 +102,25 @@ def test_gradient_descent_decreases_validation_loss(nys, subsample):
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 def test_adjoint_against_unrolled_differentiation(nys, kind):
     """Cross-check of the implicit adjoint against differentiating through the PCG
-    iterations (the oracle's unrolled gradient, 60 iterations: converged).  The GPU
-    adjoint at tolerance tol lands within 10 tol of it (relative) for every tol; the
-    unrolled gradient truncated at the forward solve's own iteration count is the
-    worse approximation at loose tolerances, which is why the adjoint is used."""
+    iterations.  Reference: the oracle's exact dense gradient, which the oracle's
+    unrolled gradient reaches once the iterations have converged.  The GPU adjoint at
+    tolerance tol is a first-order perturbation of it: the forward and adjoint solves
+    each stop at relative residual tol, so their relative errors, and the gradient's,
+    are at most a small multiple of cond(K + lambda I) tol.  The unrolled gradient
+    truncated at the forward solve's own iteration count is the worse approximation
+    at loose tolerances, which is why the adjoint is used."""
     from paper_2609_08136_amd import autograd as ag
     w = ni.small_problem(900, 5, seed=61, kind=kind, r=40)
     X, y, Xv, yv = w.X[:750], w.B[:750, 0], w.X[750:], w.B[750:, 0]
     lam, sig = 0.5, 2.0
     Om = ni.gaussian_test_matrix(750, 40, 61)
     K = o.kernel_matrix(X, X, kind, sig)
+    ev = np.linalg.eigvalsh(K)
+    cond = (ev[-1] + lam) / (max(ev[0], 0.0) + lam)
     U, lh, _ = o.nystrom(lambda V: K @ V, Om)
-    _, gl_ref, gs_ref = o.unrolled_validation_grad(X, y, Xv, yv, kind, sig, lam, U, lh, 60)
+    _, gl_ref, gs_ref, _, _ = o.validation_loss_grad(X, y, Xv, yv, kind, sig, lam)
+    _, ul, us = o.unrolled_validation_grad(X, y, Xv, yv, kind, sig, lam, U, lh, 200)
+    assert abs(ul - gl_ref) <= 1e-9 * abs(gl_ref) and abs(us - gs_ref) <= 1e-9 * abs(gs_ref)
     tX, ty, tXv, tyv = T(X), T(y), T(Xv), T(yv)
     P = nys.build_preconditioner(tX, T(Om), kind, sig, nys.FP64)
     for tol in (1e-4, 1e-6, 1e-10):
@@ -128,7 +135,7 @@ def test_adjoint_against_unrolled_differentiation(nys, kind):
         e_adj = max(abs(gl - gl_ref) / abs(gl_ref), abs(gs - gs_ref) / abs(gs_ref))
         e_unr = max(abs(ul - gl_ref) / abs(gl_ref), abs(us - gs_ref) / abs(gs_ref))
         print(f"kind {kind} tol {tol:g}: {k} iterations; adjoint rel err {e_adj:.2e}, unrolled-at-{k} rel err "
-              f"{e_unr:.2e}", flush=True)
-        assert e_adj <= 10 * tol + 1e-9
+              f"{e_unr:.2e}; cond {cond:.1f}", flush=True)
+        assert e_adj <= 4 * cond * tol + 1e-9
         if tol >= 1e-6:
             assert e_unr > e_adj

@@ -528,3 +528,122 @@ def test_unrolled_gradient_matches_differences_of_the_truncated_loss():
     assert gs == pytest.approx(fs, rel=1e-6)
     _, dlam, dsig, _, _ = o.validation_loss_grad(X, y, Xv, yv, o.RBF, sig, lam)
     assert abs(gs - dsig) > 1e-4 * abs(dsig)
+
+
+# ---------------------------------------------------------------- ridge regression
+
+def test_sorf_factor_against_explicit_hadamard():
+    """The SORF factor equals H D1 H D2 H D3 built from scipy's Hadamard matrix, and
+    has orthonormal columns."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(3)
+    n = 64
+    signs = rng.choice(np.array([-1.0, 1.0]), size=(3, n))
+    H = sl.hadamard(n) / math.sqrt(n)
+    S = H @ np.diag(signs[0]) @ H @ np.diag(signs[1]) @ H @ np.diag(signs[2])
+    cols = ni.sorf_columns(n, 40, signs)
+    assert np.allclose(cols, S[:, :40], atol=1e-13)
+    assert np.allclose(cols.T @ cols, np.eye(40), atol=1e-13)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 2.0])
+def test_ridge_spectrum_and_closed_form(alpha):
+    """X^T X + lam I has eigenvalues i^-alpha + lam (the paper's statement for n >= p),
+    and the direct solution is the closed form V diag(s / (s^2 + lam)) U^T y."""
+    pr = ni.ridge_problem(256, 128, alpha, seed=4)
+    lam = 1e-3
+    ev = np.sort(np.linalg.eigvalsh(pr.X.T @ pr.X + lam * np.eye(128)))[::-1]
+    want = np.arange(1, 129) ** (-alpha) + lam
+    assert np.allclose(ev, want, rtol=1e-10, atol=1e-13)
+    w = o.ridge_direct(pr.X, pr.y, lam)
+    closed = pr.V @ ((pr.sigma / (pr.sigma ** 2 + lam)) * (pr.U.T @ pr.y))
+    assert np.linalg.norm(w - closed) <= 1e-9 * np.linalg.norm(closed)
+    assert abs(np.linalg.norm(pr.y) - 1.0) < 1e-12
+
+
+def test_ridge_nyspcg_beats_cg_when_ill_conditioned():
+    """The oracle's NysPCG on the normal operator converges to the direct solution, in
+    far fewer iterations than CG when the spectrum decays fast and lambda is small."""
+    pr = ni.ridge_problem(512, 512, 2.0, seed=5)
+    lam = 1e-6
+    apply_K = o.ridge_normal_apply(pr.X)
+    U, lh, _ = o.nystrom(apply_K, ni.gaussian_test_matrix(512, 64, 5))
+    A = lambda v: apply_K(v) + lam * v
+    b = pr.X.T @ pr.y
+    x, it_p, _ = o.pcg(A, b, lambda r: o.precond_apply(U, lh, lam, r), tol=1e-10, max_iters=5000)
+    _, it_cg, _ = o.pcg(A, b, None, tol=1e-10, max_iters=5000)
+    ref = o.ridge_direct(pr.X, pr.y, lam)
+    assert np.linalg.norm(x - ref) <= 1e-4 * np.linalg.norm(ref)
+    assert it_p * 5 < it_cg
+
+
+# ---------------------------------------------------------------- NysADMM (bounded elastic net)
+
+def _bvls_elastic_net(X, y, lam1, lam2, lo=0.0, hi=1.0):
+    """Exact bounded elastic net on [0, 1]^p (where |w|_1 = 1^T w) by SciPy's bounded
+    least squares: (1/2n)|X_c w - y_c|^2 + lam2/2|w|^2 + lam1 1^T w equals, up to a
+    constant, 1/2 |[X_c / sqrt(n); sqrt(lam2) I] w - [y_c / sqrt(n); -lam1/sqrt(lam2) 1]|^2."""
+    from scipy.optimize import lsq_linear
+    n, p = X.shape
+    Xc = X - X.mean(axis=0)
+    yc = y - y.mean()
+    A = np.vstack([Xc / math.sqrt(n), math.sqrt(lam2) * np.eye(p)])
+    b = np.concatenate([yc / math.sqrt(n), -lam1 / math.sqrt(lam2) * np.ones(p)])
+    return lsq_linear(A, b, bounds=(lo, hi), method="bvls", tol=1e-14).x
+
+
+def test_elastic_net_prox_against_brute_force():
+    rng = np.random.default_rng(70)
+    grid = np.linspace(-0.5, 1.5, 400001)
+    for _ in range(30):
+        v, rho, l1, l2 = rng.normal(0, 1), rng.uniform(0.1, 3), rng.uniform(0, 0.5), rng.uniform(0, 0.5)
+        zs = np.clip(grid, 0.0, 1.0)
+        obj = l1 * np.abs(zs) + 0.5 * l2 * zs ** 2 + 0.5 * rho * (zs - v) ** 2
+        z_bf = zs[np.argmin(obj)]
+        z = float(o.elastic_net_prox(np.array([v]), rho, l1, l2, 0.0, 1.0)[0])
+        assert abs(z - z_bf) <= 1e-5
+
+
+def test_kkt_measure_vanishes_at_the_exact_solution_only():
+    pr = ni.elastic_net_problem(600, 8, 40, seed=71)
+    w = _bvls_elastic_net(pr.X, pr.y, pr.lam1, pr.lam2)
+    assert o.elastic_net_kkt(pr.X, pr.y, w, pr.lam1, pr.lam2) <= 1e-10
+    assert 0.0 < w.max() and w.min() == 0.0                     # some bounds are active
+    w2 = w.copy()
+    w2[np.argmax(w)] *= 0.9
+    assert o.elastic_net_kkt(pr.X, pr.y, w2, pr.lam1, pr.lam2) > 1e-4
+
+
+@pytest.mark.parametrize("seed", [72, 73])
+def test_nysadmm_reaches_the_bounded_least_squares_solution(seed):
+    """The oracle's NysADMM, run to tight tolerances, lands on the exact solution of the
+    bounded problem (computed independently by SciPy's BVLS) and on its intercept; at
+    the paper's default tolerances it meets its own stopping rule with a small
+    stationarity violation."""
+    pr = ni.elastic_net_problem(800, 8, 48, seed=seed)
+    ref = _bvls_elastic_net(pr.X, pr.y, pr.lam1, pr.lam2)
+    res = o.nysadmm_elastic_net(pr.X, pr.y, pr.lam1, pr.lam2, rank=16, eps_abs=1e-10, eps_rel=1e-10,
+                                max_iters=3000, seed=seed)
+    assert res["converged"]
+    assert np.max(np.abs(res["w"] - ref)) <= 1e-7
+    b_ref = pr.y.mean() - pr.X.mean(axis=0) @ ref
+    assert abs(res["b"] - b_ref) <= 1e-7
+    assert o.elastic_net_kkt(pr.X, pr.y, res["w"], pr.lam1, pr.lam2) <= 1e-8
+    obj_ref = o.elastic_net_objective(pr.X, pr.y, ref, b_ref, pr.lam1, pr.lam2)
+    assert abs(o.elastic_net_objective(pr.X, pr.y, res["w"], res["b"], pr.lam1, pr.lam2) - obj_ref) <= 1e-9
+    loose = o.nysadmm_elastic_net(pr.X, pr.y, pr.lam1, pr.lam2, rank=16, seed=seed)
+    assert loose["converged"] and loose["iters"] < res["iters"]
+    assert o.elastic_net_kkt(pr.X, pr.y, loose["w"], pr.lam1, pr.lam2) <= 1e-2
+
+
+def test_nysadmm_without_penalties_or_active_bounds_is_ridge():
+    """lam1 = 0 and bounds that never bind: the fixed point is the ridge solution
+    (X_c^T X_c / n + lam2 I)^{-1} X_c^T y_c / n."""
+    pr = ni.elastic_net_problem(500, 6, 30, seed=74)
+    lam2 = 0.05
+    res = o.nysadmm_elastic_net(pr.X, pr.y, 0.0, lam2, lo=-1e6, hi=1e6, rank=10, eps_abs=1e-11, eps_rel=1e-11,
+                                max_iters=3000, seed=74)
+    Xc = pr.X - pr.X.mean(axis=0)
+    yc = pr.y - pr.y.mean()
+    ref = np.linalg.solve(Xc.T @ Xc / 500 + lam2 * np.eye(30), Xc.T @ yc / 500)
+    assert res["converged"] and np.max(np.abs(res["w"] - ref)) <= 1e-8
