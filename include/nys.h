@@ -98,7 +98,8 @@ typedef enum {
   NYS_OP_KERNEL_DOT = 7,
   NYS_OP_PRECOND_ADAPTIVE = 8,
   NYS_OP_RIDGE_SKETCH = 9,
-  NYS_OP_RIDGE_SOLVE = 10
+  NYS_OP_RIDGE_SOLVE = 10,
+  NYS_OP_ADMM_ELASTIC_NET = 11
 } nys_op;
 
 /* Kernel function: kind (nys_kind) and bandwidth sigma > 0. */
@@ -234,6 +235,7 @@ typedef struct {
  *   RIDGE_SKETCH:  n = rows of X, n2 = p, r
  *   RIDGE_SOLVE:   n = rows of X, n2 = p, d = nrhs, r (0 if no preconditioner),
  *                  m = nlam * nrhs
+ *   ADMM_ELASTIC_NET: n = rows of X, n2 = p, r = preconditioner rank
  * Returns NYS_OK and *bytes, or NYS_EINVAL. */
 int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_t r, int32_t m,
                             int32_t prec, size_t *bytes);
@@ -457,6 +459,66 @@ int32_t nys_ridge_sketch(const double *X, int64_t n, int64_t p, const double *Om
 int32_t nys_ridge_solve(const double *X, int64_t n, int64_t p, const double *Yt, int32_t nrhs,
                         const double *lambdas, int32_t nlam, const nys_precond *P, const nys_pcg_opts *opts,
                         double *W, nys_col_info *info, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- NysADMM on the bounded elastic net -----------------------------------
+ * min over w, b of (1/2n)|X w + b 1 - y|^2 + lam1 |w|_1 + lam2/2 |w|^2 subject to
+ * lo <= w <= hi (eq. experiment-bounded-en; the paper's instances use [0, 1]), by
+ * ADMM on the splitting x = z (section "Splitting for ADMM") with NysPCG solving
+ * every x-subproblem.  X is dense (n x p, row-major, device); the intercept is
+ * unregularised and eliminated by centring (the library forms X - 1 mu^T in the
+ * workspace), and the Hessian H = X_c^T X_c / n is applied matrix-free through two
+ * float64 rocBLAS products, never formed.  Iteration k = 1, 2, ...:
+ *   - every precond_update_freq iterations a fresh Nystrom approximation of H,
+ *     test matrix nys_test_matrix(seed + refresh count, p, rank);
+ *   - (H + (rho + sigma) I) x = X_c^T y / n + rho (z - u) + sigma x_prev by NysPCG
+ *     warm-started at x_prev, to relative residual
+ *     min(1, sqrt(|r_pri| |r_dual|)) k^-gamma (previous residuals; 1 at k = 1);
+ *   - over-relaxation xh = alpha x + (1 - alpha) z, the proximal step
+ *     z = clip(soft(xh + u, lam1/rho) rho/(rho + lam2), lo, hi), u += xh - z;
+ *   - r_pri = x - z, r_dual = grad f(x) + rho u; stop when
+ *     |r_pri| <= sqrt(p) eps_abs + eps_rel max(|x|, |z|) and
+ *     |r_dual| <= sqrt(p) eps_abs + eps_rel |rho u| (table tab:rlaopt-admm-stopping);
+ *   - every rho_update_freq iterations: rho times rho_update_factor (u divided by
+ *     it) when |r_pri| > rho_update_threshold |r_dual|, the reverse when
+ *     |r_dual| > rho_update_threshold |r_pri|.
+ * Configuration fields and defaults follow table tab:rlaopt-admm-config (rank 50,
+ * the NysADMM default preconditioner); a zero field takes its default. */
+typedef struct {
+  double rho;                   /* initial penalty (1.0) */
+  double rho_update_factor;     /* (2.0) */
+  double rho_update_threshold;  /* (10.0) */
+  int32_t rho_update_freq;      /* iterations between penalty updates (25) */
+  int32_t precond_update_freq;  /* iterations between preconditioner refreshes (20) */
+  double alpha;                 /* over-relaxation, 0 < alpha < 2 (1.6) */
+  double sigma;                 /* proximal regularisation of the x-subproblem (1e-6) */
+  double gamma;                 /* decay exponent of the subproblem tolerance, > 1 (1.2) */
+  int32_t rank;                 /* Nystrom rank, 1 <= rank <= min(p, 1024) (50) */
+  int32_t max_iters;            /* ADMM iterations (1000) */
+  double eps_abs;               /* (1e-4) */
+  double eps_rel;               /* (1e-4) */
+  uint64_t seed;                /* test-matrix seed (0 is a valid seed) */
+  int32_t pcg_max_iters;        /* per subproblem (1000) */
+  int32_t reserved;
+} nys_admm_config;
+
+typedef struct {
+  int32_t iters;           /* ADMM iterations run */
+  int32_t converged;       /* 1 when both residual tests passed */
+  int64_t pcg_iters;       /* PCG iterations over all subproblems */
+  double r_pri, r_dual;    /* final residual norms */
+  double eps_pri, eps_dual;/* and their tolerances */
+  double rho;              /* final penalty */
+  double intercept;        /* b = mean(y) - mu^T w */
+} nys_admm_info;
+
+/* W (device, p): the solution z (within the box).  y device (n).  info HOST.
+ * Returns NYS_OK (converged), NYS_NOT_CONVERGED (max_iters reached; W and info hold
+ * the last iterate), NYS_EINVAL (sizes, lo > hi, negative penalties, a config field
+ * out of range), NYS_ENOMEM (workspace too small), NYS_ENOTPD / NYS_ENUMERIC (a
+ * preconditioner build failed), NYS_EHIP. */
+int32_t nys_admm_elastic_net(const double *X, int64_t n, int64_t p, const double *y, double lam1, double lam2,
+                             double lo, double hi, const nys_admm_config *cfg, double *W, nys_admm_info *info,
+                             void *ws, size_t ws_bytes, void *stream);
 
 /* Thread-local description of the last non-zero status ("" if none). */
 const char *nys_last_error(void);

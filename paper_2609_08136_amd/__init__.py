@@ -25,13 +25,13 @@ PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 (OP_KERNEL_MATVEC, OP_SKETCH, OP_PRECOND_BUILD, OP_PRECOND_APPLY, OP_SOLVE, OP_BACKWARD, OP_AUTOTUNE,
- OP_KERNEL_DOT, OP_PRECOND_ADAPTIVE, OP_RIDGE_SKETCH, OP_RIDGE_SOLVE) = range(11)
+ OP_KERNEL_DOT, OP_PRECOND_ADAPTIVE, OP_RIDGE_SKETCH, OP_RIDGE_SOLVE, OP_ADMM_ELASTIC_NET) = range(12)
 
 EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "kernel_dot", "nys_test_matrix", "nys_sketch", "nys_precond_build",
            "nys_precond_adaptive",
            "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_autotune", "nys_set_tile",
            "nys_clear_tiles", "nys_plan_chunks", "nys_peak_probe", "nys_ridge_sketch", "nys_ridge_solve",
-           "nys_last_error", "nys_version")
+           "nys_admm_elastic_net", "nys_last_error", "nys_version")
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -57,6 +57,19 @@ class NysPCGOpts(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("max_iters", c_i32), ("prec", c_i32), ("refine_every", c_i32),
                 ("refine_mode", c_i32), ("check_true", c_i32), ("max_refinements", c_i32),
                 ("refine_reduction", c_f64), ("refine_join", c_f64)]
+
+
+class NysAdmmConfig(ctypes.Structure):
+    """nys_admm_config (table tab:rlaopt-admm-config; zero fields take their defaults)."""
+    _fields_ = [("rho", c_f64), ("rho_update_factor", c_f64), ("rho_update_threshold", c_f64),
+                ("rho_update_freq", c_i32), ("precond_update_freq", c_i32), ("alpha", c_f64), ("sigma", c_f64),
+                ("gamma", c_f64), ("rank", c_i32), ("max_iters", c_i32), ("eps_abs", c_f64), ("eps_rel", c_f64),
+                ("seed", ctypes.c_uint64), ("pcg_max_iters", c_i32), ("reserved", c_i32)]
+
+
+class NysAdmmInfo(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("converged", c_i32), ("pcg_iters", c_i64), ("r_pri", c_f64), ("r_dual", c_f64),
+                ("eps_pri", c_f64), ("eps_dual", c_f64), ("rho", c_f64), ("intercept", c_f64)]
 
 
 class NysColInfo(ctypes.Structure):
@@ -116,6 +129,9 @@ def load(path: str | None = None):
     lib.nys_plan_chunks.argtypes = [c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
     lib.nys_peak_probe.argtypes = [c_i32, c_i32, ctypes.POINTER(c_f64), c_vp, c_sz, c_vp]
     lib.nys_ridge_sketch.argtypes = [c_vp, c_i64, c_i64, c_vp, ctypes.c_uint64, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]
+    lib.nys_admm_elastic_net.argtypes = [c_vp, c_i64, c_i64, c_vp, c_f64, c_f64, c_f64, c_f64,
+                                         ctypes.POINTER(NysAdmmConfig), c_vp, ctypes.POINTER(NysAdmmInfo), c_vp,
+                                         c_sz, c_vp]
     lib.nys_ridge_solve.argtypes = [c_vp, c_i64, c_i64, c_vp, c_i32, ctypes.POINTER(c_f64), c_i32,
                                     ctypes.POINTER(NysPrecondC), ctypes.POINTER(NysPCGOpts), c_vp,
                                     ctypes.POINTER(NysColInfo), c_vp, c_sz, c_vp]
@@ -491,6 +507,34 @@ def nys_ridge_solve(X, Y, lambdas, P: Preconditioner | None = None, tol: float =
                              ws.data_ptr(), ws.numel(), _stream())
     _check(rc)
     return (W.reshape(-1) if (vec and nlam == 1) else W), _info_list(info, m), rc
+
+
+def nys_admm_elastic_net(X, y, lam1: float, lam2: float, lo: float = 0.0, hi: float = 1.0, **config):
+    """NysADMM on the bounded elastic net (eq. experiment-bounded-en) with the dense data
+    matrix X (n x p float64 CUDA) and targets y (n).  Keyword arguments are fields of
+    nys_admm_config (rho, alpha, sigma, gamma, rank, max_iters, eps_abs, eps_rel, seed,
+    ...); omitted ones take the paper's defaults.  Returns (w, info dict, status)."""
+    lib = load()
+    _need_cuda(X, torch.float64, "X")
+    yv = y.reshape(-1)
+    _need_cuda(yv, torch.float64, "y")
+    n, p = X.shape
+    if yv.numel() != n:
+        raise ValueError("y must have one entry per row of X")
+    cfg = NysAdmmConfig()
+    for k, v in config.items():
+        if k not in dict(NysAdmmConfig._fields_):
+            raise TypeError(f"unknown nys_admm_config field {k!r}")
+        setattr(cfg, k, v)
+    rank = cfg.rank or min(50, p)
+    W = torch.empty(p, dtype=torch.float64, device=X.device)
+    info = NysAdmmInfo()
+    ws = _workspace(nys_workspace_bytes(OP_ADMM_ELASTIC_NET, n, p, 0, rank), X.device)
+    rc = lib.nys_admm_elastic_net(X.data_ptr(), n, p, yv.data_ptr(), float(lam1), float(lam2), float(lo), float(hi),
+                                  ctypes.byref(cfg), W.data_ptr(), ctypes.byref(info), ws.data_ptr(), ws.numel(),
+                                  _stream())
+    _check(rc)
+    return W, {f: getattr(info, f) for f, _ in NysAdmmInfo._fields_}, rc
 
 
 # ------------------------------------------------------------------------------ autotuner

@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include "admm.h"
+#include "gemv.h"
 #include "pcg.h"
 
 namespace nys {
@@ -401,7 +403,9 @@ struct RidgeOp {
   const double *X;
   int64_t nrows, p;
   double *T;            // nrows x m scratch
+  double *part;         // gemv_partial_elems(nrows, p) scratch of the one-column product
   rocblas_handle h = nullptr;
+  double scale = 1.0;   // the operator is scale * X^T X
   int32_t prepare(hipStream_t s) {
     NYS_RETURN_IF(blas_handle(&h));
     if (rocblas_set_stream(h, s) != rocblas_status_success) {
@@ -418,20 +422,14 @@ struct RidgeOp {
     NYS_RETURN_IF(prepare(s));
     const double one = 1.0, zero = 0.0;
     if (m == 1) {
-      // one column: two matrix-vector products, each a single pass over X
-      if (rocblas_dgemv_64(h, rocblas_operation_transpose, (int64_t)p, (int64_t)nrows, &one, X, (int64_t)p,
-                        V, ldv, &zero, T, 1) != rocblas_status_success ||
-          rocblas_dgemv_64(h, rocblas_operation_none, (int64_t)p, (int64_t)nrows, &one, X, (int64_t)p, T, 1,
-                        &zero, Out, ldo) != rocblas_status_success) {
-        set_error("rocblas_dgemv failed in the ridge operator");
-        return NYS_EHIP;
-      }
-      return NYS_OK;
+      // one column: two matrix-vector products of our own, each a single pass over X
+      NYS_RETURN_IF(launch_rowdot(X, nrows, p, V, ldv, T, s));
+      return launch_coltrans(X, nrows, p, T, scale, Out, ldo, part, s);
     }
     if (rocblas_dgemm_64(h, rocblas_operation_none, rocblas_operation_none, m, (int64_t)nrows, (int64_t)p, &one,
                       V, ldv, X, (int64_t)p, &zero, T, m) != rocblas_status_success ||
         rocblas_dgemm_64(h, rocblas_operation_none, rocblas_operation_transpose, m, (int64_t)p, (int64_t)nrows,
-                      &one, T, m, X, (int64_t)p, &zero, Out, ldo) != rocblas_status_success) {
+                      &scale, T, m, X, (int64_t)p, &zero, Out, ldo) != rocblas_status_success) {
       set_error("rocblas_dgemm failed in the ridge operator");
       return NYS_EHIP;
     }
@@ -443,6 +441,7 @@ struct RidgeOp {
 // solve, the right-hand sides X^T y (p x nrhs); for the sketch, the Cholesky QR.
 struct RidgeSketchPlan {
   double *G = nullptr, *Gpart = nullptr, *Linv = nullptr, *LinvT = nullptr, *Om = nullptr, *T = nullptr;
+  double *part = nullptr;
   int *flag = nullptr;
 };
 void plan_ridge_sketch(RidgeSketchPlan &p, int64_t n, int64_t pd, int r, Arena &ws) {
@@ -453,16 +452,44 @@ void plan_ridge_sketch(RidgeSketchPlan &p, int64_t n, int64_t pd, int r, Arena &
   p.LinvT = ws.take<double>((size_t)r * r);
   p.Om = ws.take<double>((size_t)pd * r);
   p.T = ws.take<double>((size_t)n * r);
+  p.part = ws.take<double>(gemv_partial_elems(n, pd));
   p.flag = ws.take<int>(4);
 }
 struct RidgeSolvePlan {
   SolvePlan sp;
-  double *T = nullptr, *B = nullptr;
+  double *T = nullptr, *B = nullptr, *part = nullptr;
 };
 void plan_ridge_solve(RidgeSolvePlan &p, int64_t n, int64_t pd, int r, int nrhs, int m, Arena &ws) {
   plan_solve(p.sp, pd, 1, r, m, NYS_FP64, false, true, ws, false);
   p.T = ws.take<double>((size_t)n * m);
   p.B = ws.take<double>((size_t)pd * nrhs);
+  p.part = ws.take<double>(gemv_partial_elems(n, pd));
+}
+
+// Q = Omega L^-T with L L^T = Omega^T Omega (Cholesky QR, float64): the orthonormalised
+// pd x r test matrix; Omega NULL draws it from the seed (nys_test_matrix).  Synchronises.
+int32_t orth_test_matrix(const double *Omega, uint64_t seed, int64_t pd, int r, RidgeSketchPlan &pl, double *Q,
+                         hipStream_t s) {
+  const int64_t cnt = pd * (int64_t)r;
+  const double *Om = Omega;
+  if (!Om) {
+    NYS_RETURN_IF(launch_gaussian(seed, cnt, pl.Om, s));
+    Om = pl.Om;
+  }
+  const int splits = gemm_tn_splits(pd, r, r);
+  NYS_RETURN_IF(gemm_tn<double>(Om, r, Om, r, pd, r, r, pl.G, r, pl.Gpart, splits, s));
+  NYS_RETURN_IF(launch_chol(pl.G, r, pl.flag, s));
+  int flag = 0;
+  NYS_CHECK_HIP(hipMemcpyAsync(&flag, pl.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_CHECK_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    set_error("the test matrix Omega is rank deficient or not finite");
+    return NYS_ENOTPD;
+  }
+  NYS_RETURN_IF(launch_trinv_lower(pl.G, pl.Linv, r, s));
+  NYS_RETURN_IF(launch_transpose(pl.Linv, pl.LinvT, r, s));
+  NYS_RETURN_IF(gemm_nn<double>(Om, r, pl.LinvT, r, pd, r, r, Q, r, 0, nullptr, 0, nullptr, s));
+  return NYS_OK;
 }
 
 // The PCG driver (solve_columns).
@@ -697,6 +724,179 @@ int32_t check_opts(const nys_pcg_opts *o) {
   return NYS_OK;
 }
 
+// ------------------------------------------------------------ NysADMM (bounded elastic net)
+struct AdmmPlan {
+  double *Xc = nullptr, *ones = nullptr, *mu = nullptr, *c = nullptr;
+  double *x = nullptr, *z = nullptr, *u = nullptr, *dx = nullptr, *rhs = nullptr, *r0 = nullptr, *Hx = nullptr;
+  double *partial = nullptr, *out = nullptr, *U = nullptr, *lam_hat = nullptr, *Q = nullptr, *Y = nullptr;
+  double *redn = nullptr;  // partials of one length-n dot product
+  RidgeSketchPlan sk;
+  BuildPlan bp;
+  SolvePlan sp;
+};
+void plan_admm(AdmmPlan &p, int64_t n, int64_t pd, int r, Arena &ws) {
+  p.Xc = ws.take<double>((size_t)n * pd);
+  p.ones = ws.take<double>((size_t)n);
+  p.redn = ws.take<double>((size_t)colred_shape(n, 1).nb);
+  for (double **v : {&p.mu, &p.c, &p.x, &p.z, &p.u, &p.dx, &p.rhs, &p.r0, &p.Hx}) *v = ws.take<double>((size_t)pd);
+  p.partial = ws.take<double>(admm_partial_elems(pd));
+  p.out = ws.take<double>(8);
+  p.U = ws.take<double>((size_t)pd * r);
+  p.lam_hat = ws.take<double>((size_t)r);
+  p.Q = ws.take<double>((size_t)pd * r);
+  p.Y = ws.take<double>((size_t)pd * r);
+  plan_ridge_sketch(p.sk, n, pd, r, ws);
+  plan_build(p.bp, pd, r, ws);
+  plan_solve(p.sp, pd, 1, r, 1, NYS_FP64, false, false, ws, false);
+}
+
+int32_t admm_config(const nys_admm_config *in, int64_t p, nys_admm_config &c) {
+  c = *in;
+  auto dflt = [](double v, double d) { return v == 0.0 ? d : v; };
+  c.rho = dflt(c.rho, 1.0);
+  c.rho_update_factor = dflt(c.rho_update_factor, 2.0);
+  c.rho_update_threshold = dflt(c.rho_update_threshold, 10.0);
+  c.alpha = dflt(c.alpha, 1.6);
+  c.sigma = dflt(c.sigma, 1e-6);
+  c.gamma = dflt(c.gamma, 1.2);
+  c.eps_abs = dflt(c.eps_abs, 1e-4);
+  c.eps_rel = dflt(c.eps_rel, 1e-4);
+  if (c.rho_update_freq == 0) c.rho_update_freq = 25;
+  if (c.precond_update_freq == 0) c.precond_update_freq = 20;
+  if (c.rank == 0) c.rank = (int32_t)std::min<int64_t>(50, p);
+  if (c.max_iters == 0) c.max_iters = 1000;
+  if (c.pcg_max_iters == 0) c.pcg_max_iters = 1000;
+  const bool fin = std::isfinite(c.rho) && std::isfinite(c.rho_update_factor) &&
+                   std::isfinite(c.rho_update_threshold) && std::isfinite(c.alpha) && std::isfinite(c.sigma) &&
+                   std::isfinite(c.gamma) && std::isfinite(c.eps_abs) && std::isfinite(c.eps_rel);
+  if (!fin || c.rho <= 0.0 || c.rho_update_factor <= 1.0 || c.rho_update_threshold < 1.0 || c.alpha <= 0.0 ||
+      c.alpha >= 2.0 || c.sigma < 0.0 || c.gamma <= 1.0 || c.eps_abs < 0.0 || c.eps_rel < 0.0 ||
+      c.eps_abs + c.eps_rel <= 0.0)
+    return einval("nys_admm_config: a parameter is out of range (rho > 0, factor > 1, threshold >= 1, "
+                  "0 < alpha < 2, sigma >= 0, gamma > 1, tolerances >= 0 and not both 0)");
+  if (c.rho_update_freq < 1 || c.precond_update_freq < 1 || c.max_iters < 1 || c.pcg_max_iters < 1)
+    return einval("nys_admm_config: iteration counts must be >= 1");
+  if (c.rank < 1 || c.rank > p || c.rank > 1024) return einval("nys_admm_config: need 1 <= rank <= min(p, 1024)");
+  return NYS_OK;
+}
+
+// The iteration of nys_admm_elastic_net (documented with its declaration).
+int32_t admm_impl(const double *X, int64_t n, int64_t pd, const double *y, double lam1, double lam2, double lo,
+                  double hi, const nys_admm_config &c, double *W, nys_admm_info *info, AdmmPlan &pl,
+                  hipStream_t s) {
+  const int r = c.rank;
+  const double inv_n = 1.0 / (double)n;
+  RidgeOp op{pl.Xc, n, pd, pl.sk.T, pl.sk.part};
+  op.scale = inv_n;
+  NYS_RETURN_IF(op.prepare(s));
+  // centring: mu = X^T 1 / n, Xc = X - 1 mu^T, c = Xc^T y / n (Xc^T 1 = 0), ybar
+  NYS_RETURN_IF(launch_fill(pl.ones, 1.0, n, s));
+  NYS_RETURN_IF(launch_coltrans(X, n, pd, pl.ones, inv_n, pl.mu, 1, pl.sk.part, s));
+  NYS_RETURN_IF(admm_center(X, pl.mu, n, pd, pl.Xc, s));
+  NYS_RETURN_IF(launch_coltrans(pl.Xc, n, pd, y, inv_n, pl.c, 1, pl.sk.part, s));
+  double ybar = 0.0;
+  NYS_RETURN_IF(dot_host(pl.ones, y, n, pl.redn, pl.out, &ybar, s));
+  ybar *= inv_n;
+  if (!std::isfinite(ybar)) {
+    set_error("nys_admm_elastic_net: NaN or Inf in y");
+    return NYS_ENUMERIC;
+  }
+  for (double *v : {pl.x, pl.z, pl.u, pl.Hx}) NYS_RETURN_IF(launch_fill(v, 0.0, pd, s));
+
+  nys_precond P{};
+  P.n = pd;
+  P.r = r;
+  P.U = pl.U;
+  P.U32 = nullptr;
+  P.lam_hat = pl.lam_hat;
+  nys_pcg_opts po{};
+  po.max_iters = c.pcg_max_iters;
+  po.prec = NYS_FP64;
+  po.refine_every = -1;
+
+  double rho = c.rho, rp = 0.0, rd = 0.0, eps_pri = 0.0, eps_dual = 0.0;
+  int64_t pcg_total = 0;
+  bool converged = false;
+  int k = 0;
+  const double sq = std::sqrt((double)pd);
+  const bool verbose = std::getenv("NYS_VERBOSE") != nullptr;
+  for (k = 1; k <= c.max_iters; ++k) {
+    if ((k - 1) % c.precond_update_freq == 0) {
+      const uint64_t sd = c.seed + (uint64_t)((k - 1) / c.precond_update_freq);
+      NYS_RETURN_IF(orth_test_matrix(nullptr, sd, pd, r, pl.sk, pl.Q, s));
+      NYS_RETURN_IF(op.apply64(pl.Q, r, r, pl.Y, r, s));
+      NYS_RETURN_IF(build_impl(pl.Y, pl.Q, pd, r, NYS_FP64, &P, pl.bp, s));
+    }
+    // x-subproblem, warm-started: solve A dx = r0 with r0 = rhs - A x_prev
+    NYS_RETURN_IF(admm_rhs(pl.c, pl.z, pl.u, pl.x, pl.Hx, rho, c.sigma, pd, pl.rhs, pl.r0, pl.partial, pl.out, s));
+    double nn[2];
+    NYS_CHECK_HIP(hipMemcpyAsync(nn, pl.out, sizeof(nn), hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    const double bn = std::sqrt(nn[0]), r0n = std::sqrt(nn[1]);
+    if (!std::isfinite(bn) || !std::isfinite(r0n)) {
+      set_error("nys_admm_elastic_net: NaN or Inf in the x-subproblem");
+      return NYS_ENUMERIC;
+    }
+    const double scale = k == 1 ? 1.0 : std::min(1.0, std::sqrt(rp * rd));
+    const double tol_k = std::max(scale * std::pow((double)k, -c.gamma), 1e-15);
+    const double *dx = nullptr;
+    if (bn > 0.0 && r0n > tol_k * bn) {
+      po.tol = tol_k * bn / r0n;
+      const double lk = rho + c.sigma;
+      nys_col_info ci{};
+      const int32_t rc = solve_columns<double>(op, pd, pl.r0, 1, &lk, 1, &P, po, pl.dx, &ci, pl.sp, s);
+      if (rc != NYS_OK && rc != NYS_NOT_CONVERGED) return rc;
+      pcg_total += ci.iters;
+      dx = pl.dx;
+    }
+    NYS_RETURN_IF(admm_update(pl.x, dx, c.alpha, pl.z, pl.u, rho, lam1, lam2, lo, hi, pd, pl.partial, s));
+    NYS_RETURN_IF(op.apply64(pl.x, 1, 1, pl.Hx, 1, s));
+    NYS_RETURN_IF(admm_dual(pl.Hx, pl.c, pl.u, rho, pd, pl.partial, pl.out, s));
+    double q[5];
+    NYS_CHECK_HIP(hipMemcpyAsync(q, pl.out, sizeof(q), hipMemcpyDeviceToHost, s));
+    NYS_CHECK_HIP(hipStreamSynchronize(s));
+    rp = std::sqrt(q[0]);
+    rd = std::sqrt(q[3]);
+    eps_pri = sq * c.eps_abs + c.eps_rel * std::max(std::sqrt(q[1]), std::sqrt(q[2]));
+    eps_dual = sq * c.eps_abs + c.eps_rel * std::sqrt(q[4]);
+    if (!std::isfinite(rp) || !std::isfinite(rd)) {
+      set_error("nys_admm_elastic_net: NaN or Inf in the residuals");
+      return NYS_ENUMERIC;
+    }
+    if (verbose) {
+      std::fprintf(stderr, "[nys] admm %d rho %.3g r_pri %.3e (%.3e) r_dual %.3e (%.3e) pcg %lld\n", k, rho, rp,
+                   eps_pri, rd, eps_dual, (long long)pcg_total);
+      std::fflush(stderr);
+    }
+    if (rp <= eps_pri && rd <= eps_dual) {
+      converged = true;
+      break;
+    }
+    if (k % c.rho_update_freq == 0) {
+      if (rp > c.rho_update_threshold * rd) {
+        rho *= c.rho_update_factor;
+        NYS_RETURN_IF(admm_scale(pl.u, 1.0 / c.rho_update_factor, pd, s));
+      } else if (rd > c.rho_update_threshold * rp) {
+        rho /= c.rho_update_factor;
+        NYS_RETURN_IF(admm_scale(pl.u, c.rho_update_factor, pd, s));
+      }
+    }
+  }
+  NYS_CHECK_HIP(hipMemcpyAsync(W, pl.z, sizeof(double) * (size_t)pd, hipMemcpyDeviceToDevice, s));
+  double muz = 0.0;
+  NYS_RETURN_IF(dot_host(pl.mu, pl.z, pd, pl.sp.red, pl.out, &muz, s));
+  info->iters = std::min(k, c.max_iters);
+  info->converged = converged ? 1 : 0;
+  info->pcg_iters = pcg_total;
+  info->r_pri = rp;
+  info->r_dual = rd;
+  info->eps_pri = eps_pri;
+  info->eps_dual = eps_dual;
+  info->rho = rho;
+  info->intercept = ybar - muz;
+  return converged ? NYS_OK : NYS_NOT_CONVERGED;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -759,6 +959,11 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
     case NYS_OP_RIDGE_SOLVE: {
       RidgeSolvePlan p;
       plan_ridge_solve(p, std::max<int64_t>(n, 1), std::max<int64_t>(n2, 1), r, std::max(d, 1), std::max(m, 1), a);
+      break;
+    }
+    case NYS_OP_ADMM_ELASTIC_NET: {
+      AdmmPlan p;
+      plan_admm(p, std::max<int64_t>(n, 1), std::max<int64_t>(n2, 1), std::max(r, 1), a);
       break;
     }
     case NYS_OP_KERNEL_DOT: {
@@ -850,8 +1055,8 @@ int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int
       best_tm = tm;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   kmv_tune_restore(saved);
   if (rc == NYS_OK) kmv_tune_set(key, m_lo, m, best_tm);
   if (rc != NYS_OK) {
@@ -1073,25 +1278,8 @@ int32_t nys_ridge_sketch(const double *X, int64_t n, int64_t p, const double *Om
   RidgeSketchPlan pl;
   plan_ridge_sketch(pl, n, p, r, a);
   NYS_RETURN_IF(check_ws(a));
-  const double *Om = Omega;
-  if (!Om) {
-    NYS_RETURN_IF(launch_gaussian(seed, cnt, pl.Om, s));
-    Om = pl.Om;
-  }
-  const int splits = gemm_tn_splits(p, r, r);
-  NYS_RETURN_IF(gemm_tn<double>(Om, r, Om, r, p, r, r, pl.G, r, pl.Gpart, splits, s));
-  NYS_RETURN_IF(launch_chol(pl.G, r, pl.flag, s));
-  int flag = 0;
-  NYS_CHECK_HIP(hipMemcpyAsync(&flag, pl.flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  NYS_CHECK_HIP(hipStreamSynchronize(s));
-  if (flag) {
-    set_error("nys_ridge_sketch: the test matrix Omega is rank deficient or not finite");
-    return NYS_ENOTPD;
-  }
-  NYS_RETURN_IF(launch_trinv_lower(pl.G, pl.Linv, r, s));
-  NYS_RETURN_IF(launch_transpose(pl.Linv, pl.LinvT, r, s));
-  NYS_RETURN_IF(gemm_nn<double>(Om, r, pl.LinvT, r, p, r, r, Q, r, 0, nullptr, 0, nullptr, s));
-  RidgeOp op{X, n, p, pl.T};
+  NYS_RETURN_IF(orth_test_matrix(Omega, seed, p, r, pl, Q, s));
+  RidgeOp op{X, n, p, pl.T, pl.part};
   NYS_RETURN_IF(op.apply64(Q, r, r, Y, r, s));
   NYS_CHECK_HIP(hipStreamSynchronize(s));
   return NYS_OK;
@@ -1117,7 +1305,7 @@ int32_t nys_ridge_solve(const double *X, int64_t n, int64_t p, const double *Yt,
   RidgeSolvePlan pl;
   plan_ridge_solve(pl, n, p, P ? P->r : 0, nrhs, m, a);
   NYS_RETURN_IF(check_ws(a));
-  RidgeOp op{X, n, p, pl.T};
+  RidgeOp op{X, n, p, pl.T, pl.part};
   NYS_RETURN_IF(op.prepare(s));
   // right-hand sides X^T y (p x nrhs)
   const double one = 1.0, zero = 0.0;
@@ -1127,6 +1315,26 @@ int32_t nys_ridge_solve(const double *X, int64_t n, int64_t p, const double *Yt,
     return NYS_EHIP;
   }
   return solve_columns<double>(op, p, pl.B, nrhs, lambdas, nlam, P, *opts, W, info, pl.sp, s);
+}
+
+int32_t nys_admm_elastic_net(const double *X, int64_t n, int64_t p, const double *y, double lam1, double lam2,
+                             double lo, double hi, const nys_admm_config *cfg, double *W, nys_admm_info *info,
+                             void *ws, size_t ws_bytes, void *stream) {
+  if (n < 1 || p < 1 || n > INT32_MAX || p > INT32_MAX) return einval("need 1 <= n, p < 2^31");
+  if (!X || !y || !cfg || !W || !info || !ws) return einval("null pointer");
+  if (!(lam1 >= 0.0) || !(lam2 >= 0.0) || !std::isfinite(lam1) || !std::isfinite(lam2))
+    return einval("lam1 and lam2 must be finite and >= 0");
+  if (!(lo <= hi) || std::isnan(lo) || std::isnan(hi)) return einval("need lo <= hi");
+  nys_admm_config c;
+  NYS_RETURN_IF(admm_config(cfg, p, c));
+  hipStream_t s = as_stream(stream);
+  Arena a;
+  a.base = reinterpret_cast<char *>(ws);
+  a.cap = ws_bytes;
+  AdmmPlan pl;
+  plan_admm(pl, n, p, c.rank, a);
+  NYS_RETURN_IF(check_ws(a));
+  return admm_impl(X, n, p, y, lam1, lam2, lo, hi, c, W, info, pl, s);
 }
 
 int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, double lambda,

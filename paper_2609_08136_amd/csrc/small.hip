@@ -242,6 +242,13 @@ int32_t jacobi_eig(double *A, double *Abuf, double *V, double *w, int r, double 
     set_error("nys_precond_build: non-finite values in the Jacobi eigensolver");
     return NYS_ENUMERIC;
   }
+  // Past the sweep cap the off-diagonal mass bounds the eigenvalue error (Weyl):
+  // up to 1e-12 of the matrix norm is harmless for a preconditioner, more is reported.
+  if (!(host_off[0] <= 1e-24 * host_off[1])) {
+    set_error("nys_precond_build: the Jacobi eigensolver did not converge in " + std::to_string(max_sweeps) +
+              " sweeps (relative off-diagonal norm " + std::to_string(std::sqrt(host_off[0] / host_off[1])) + ")");
+    return NYS_ENUMERIC;
+  }
   hipLaunchKernelGGL(diag_kernel, dim3((unsigned)ceil_div(r, 256)), dim3(256), 0, s, Ac, w, r);
   NYS_LAUNCH_CHECK();
   if (Vc != V) NYS_CHECK_HIP(hipMemcpyAsync(V, Vc, sizeof(double) * tot, hipMemcpyDeviceToDevice, s));

@@ -236,3 +236,23 @@ def test_kernel_dot_argument_errors(lib):
     assert call(u=None) == nys.EINVAL
     assert lib.kernel_dot(k, 0, FAKE, 10, FAKE, 10, 3, FAKE, FAKE, ctypes.byref(out), FAKE, 0, None) == nys.ENOMEM
     assert nys.nys_workspace_bytes(nys.OP_KERNEL_DOT, 1000, 2000, 16) > 0
+
+
+def test_admm_argument_errors(lib):
+    """nys_admm_elastic_net rejects bad sizes, penalties, bounds and configuration
+    fields before touching the device."""
+    cfg = nys.NysAdmmConfig()
+    info = nys.NysAdmmInfo()
+    def call(n=10, p=4, lam1=0.1, lam2=0.1, lo=0.0, hi=1.0, c=None, W=FAKE):
+        return lib.nys_admm_elastic_net(FAKE, n, p, FAKE, lam1, lam2, lo, hi, ctypes.byref(c or cfg), W,
+                                        ctypes.byref(info), FAKE, 1 << 30, None)
+    assert call(n=0) == nys.EINVAL
+    assert call(W=None) == nys.EINVAL
+    assert call(lam1=-1.0) == nys.EINVAL
+    assert call(lam2=float("nan")) == nys.EINVAL
+    assert call(lo=1.0, hi=0.0) == nys.EINVAL
+    for field, bad in (("alpha", 2.0), ("alpha", -0.5), ("gamma", 1.0), ("rho", -1.0), ("rank", 5),
+                       ("rho_update_factor", 0.5), ("sigma", -1e-3), ("max_iters", -1)):
+        c = nys.NysAdmmConfig()
+        setattr(c, field, bad)
+        assert call(c=c) == nys.EINVAL, field
