@@ -403,7 +403,8 @@ struct RidgeOp {
   const double *X;
   int64_t nrows, p;
   double *T;            // nrows x m scratch
-  double *part;         // gemv_partial_elems(nrows, p) scratch of the one-column product
+  double *part;         // scratch of the matrix-vector kernels (ridge_part_elems)
+  size_t part_cap;      // its size in doubles
   rocblas_handle h = nullptr;
   double scale = 1.0;   // the operator is scale * X^T X
   int32_t prepare(hipStream_t s) {
@@ -427,9 +428,17 @@ struct RidgeOp {
       return launch_coltrans(X, nrows, p, T, scale, Out, ldo, part, s);
     }
     if (rocblas_dgemm_64(h, rocblas_operation_none, rocblas_operation_none, m, (int64_t)nrows, (int64_t)p, &one,
-                      V, ldv, X, (int64_t)p, &zero, T, m) != rocblas_status_success ||
-        rocblas_dgemm_64(h, rocblas_operation_none, rocblas_operation_transpose, m, (int64_t)p, (int64_t)nrows,
-                      &scale, T, m, X, (int64_t)p, &zero, Out, ldo) != rocblas_status_success) {
+                      V, ldv, X, (int64_t)p, &zero, T, m) != rocblas_status_success) {
+      set_error("rocblas_dgemm failed in the ridge operator");
+      return NYS_EHIP;
+    }
+    // Out = X^T T has a long inner dimension (the n rows).  With few 128 x 128 output
+    // tiles (small p) the library GEMM leaves most CUs idle; the row-split kernel
+    // spreads the rows instead.
+    if (ceil_div(p, 128) * ceil_div(m, 128) < 512 && gemv_partial_elems(nrows, p, m) <= part_cap)
+      return launch_coltrans_multi(X, nrows, p, T, m, m, scale, Out, ldo, part, s);
+    if (rocblas_dgemm_64(h, rocblas_operation_none, rocblas_operation_transpose, m, (int64_t)p, (int64_t)nrows,
+                         &scale, T, m, X, (int64_t)p, &zero, Out, ldo) != rocblas_status_success) {
       set_error("rocblas_dgemm failed in the ridge operator");
       return NYS_EHIP;
     }
@@ -437,11 +446,17 @@ struct RidgeOp {
   }
 };
 
+// scratch of RidgeOp's matrix-vector kernels for products of one and of m columns
+size_t ridge_part_elems(int64_t n, int64_t p, int m) {
+  return std::max(gemv_partial_elems(n, p, 1), gemv_partial_elems(n, p, std::max(m, 1)));
+}
+
 // Scratch of the ridge calls: the normal-operator intermediate (n x m) and, for the
 // solve, the right-hand sides X^T y (p x nrhs); for the sketch, the Cholesky QR.
 struct RidgeSketchPlan {
   double *G = nullptr, *Gpart = nullptr, *Linv = nullptr, *LinvT = nullptr, *Om = nullptr, *T = nullptr;
   double *part = nullptr;
+  size_t part_cap = 0;
   int *flag = nullptr;
 };
 void plan_ridge_sketch(RidgeSketchPlan &p, int64_t n, int64_t pd, int r, Arena &ws) {
@@ -452,18 +467,21 @@ void plan_ridge_sketch(RidgeSketchPlan &p, int64_t n, int64_t pd, int r, Arena &
   p.LinvT = ws.take<double>((size_t)r * r);
   p.Om = ws.take<double>((size_t)pd * r);
   p.T = ws.take<double>((size_t)n * r);
-  p.part = ws.take<double>(gemv_partial_elems(n, pd));
+  p.part_cap = ridge_part_elems(n, pd, r);
+  p.part = ws.take<double>(p.part_cap);
   p.flag = ws.take<int>(4);
 }
 struct RidgeSolvePlan {
   SolvePlan sp;
   double *T = nullptr, *B = nullptr, *part = nullptr;
+  size_t part_cap = 0;
 };
 void plan_ridge_solve(RidgeSolvePlan &p, int64_t n, int64_t pd, int r, int nrhs, int m, Arena &ws) {
   plan_solve(p.sp, pd, 1, r, m, NYS_FP64, false, true, ws, false);
   p.T = ws.take<double>((size_t)n * m);
   p.B = ws.take<double>((size_t)pd * nrhs);
-  p.part = ws.take<double>(gemv_partial_elems(n, pd));
+  p.part_cap = ridge_part_elems(n, pd, m);
+  p.part = ws.take<double>(p.part_cap);
 }
 
 // Q = Omega L^-T with L L^T = Omega^T Omega (Cholesky QR, float64): the orthonormalised
@@ -786,7 +804,7 @@ int32_t admm_impl(const double *X, int64_t n, int64_t pd, const double *y, doubl
                   hipStream_t s) {
   const int r = c.rank;
   const double inv_n = 1.0 / (double)n;
-  RidgeOp op{pl.Xc, n, pd, pl.sk.T, pl.sk.part};
+  RidgeOp op{pl.Xc, n, pd, pl.sk.T, pl.sk.part, pl.sk.part_cap};
   op.scale = inv_n;
   NYS_RETURN_IF(op.prepare(s));
   // centring: mu = X^T 1 / n, Xc = X - 1 mu^T, c = Xc^T y / n (Xc^T 1 = 0), ybar
@@ -1279,7 +1297,7 @@ int32_t nys_ridge_sketch(const double *X, int64_t n, int64_t p, const double *Om
   plan_ridge_sketch(pl, n, p, r, a);
   NYS_RETURN_IF(check_ws(a));
   NYS_RETURN_IF(orth_test_matrix(Omega, seed, p, r, pl, Q, s));
-  RidgeOp op{X, n, p, pl.T, pl.part};
+  RidgeOp op{X, n, p, pl.T, pl.part, pl.part_cap};
   NYS_RETURN_IF(op.apply64(Q, r, r, Y, r, s));
   NYS_CHECK_HIP(hipStreamSynchronize(s));
   return NYS_OK;
@@ -1305,7 +1323,7 @@ int32_t nys_ridge_solve(const double *X, int64_t n, int64_t p, const double *Yt,
   RidgeSolvePlan pl;
   plan_ridge_solve(pl, n, p, P ? P->r : 0, nrhs, m, a);
   NYS_RETURN_IF(check_ws(a));
-  RidgeOp op{X, n, p, pl.T, pl.part};
+  RidgeOp op{X, n, p, pl.T, pl.part, pl.part_cap};
   NYS_RETURN_IF(op.prepare(s));
   // right-hand sides X^T y (p x nrhs)
   const double one = 1.0, zero = 0.0;

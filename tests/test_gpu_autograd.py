@@ -77,13 +77,27 @@ def test_kernel_product_backward_matches_oracle(nys):
 
 def test_gradient_descent_decreases_validation_loss(nys, subsample):
     """20 steps of gradient descent on (log lambda, log sigma), step 0.05, halved when
-    the loss would increase; the loss must decrease monotonically."""
+    the loss would increase.  Independently of that search: a short step along -g
+    lowers the loss by |g|^2 per unit step to first order (the measured slope is within
+    10% of it, so the gradient is a descent direction of the right size), the first
+    accepted step meets the Armijo condition L(theta - eta g) <= L - 1e-4 eta |g|^2, and
+    the 20 steps lower the loss by at least 0.1%."""
     from paper_2609_08136_amd import autograd as ag
     X, y, Xv, yv, lam, sig, kind = subsample
     theta = np.array([math.log(lam), math.log(sig)])
     eta = 0.05
     L, gl, gs = loss_and_grad(nys, ag, X, y, Xv, yv, lam, sig, kind, r=100)
+    g0 = np.array([gl, gs])
+    g2 = float(g0 @ g0)
+    h = 1e-4 / math.sqrt(g2)
+    lo_, hi_ = theta - h * g0, theta + h * g0
+    Lm = loss_and_grad(nys, ag, X, y, Xv, yv, math.exp(lo_[0]), math.exp(lo_[1]), kind, r=100)[0]
+    Lp = loss_and_grad(nys, ag, X, y, Xv, yv, math.exp(hi_[0]), math.exp(hi_[1]), kind, r=100)[0]
+    slope = (Lm - Lp) / (2 * h)          # central difference along -g
+    print(f"slope along -g {slope:.6e} vs -|g|^2 {-g2:.6e}")
+    assert -1.1 * g2 <= slope <= -0.9 * g2
     hist = [L]
+    first = True
     for step in range(20):
         g = np.array([gl, gs])
         while True:
@@ -92,11 +106,14 @@ def test_gradient_descent_decreases_validation_loss(nys, subsample):
             if Lc <= L or eta < 1e-6:
                 break
             eta *= 0.5
+        if first:
+            assert Lc <= L - 1e-4 * eta * float(g @ g)
+            first = False
         theta, L, gl, gs = cand, Lc, glc, gsc
         hist.append(L)
     print("validation loss:", " ".join(f"{v:.6f}" for v in hist), "eta", eta)
     assert all(b <= a for a, b in zip(hist, hist[1:]))
-    assert hist[-1] < hist[0]
+    assert hist[-1] <= hist[0] * (1 - 1e-3)
 
 
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
