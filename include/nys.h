@@ -199,6 +199,13 @@ typedef struct {
  *                  target joins the same float64 product (0: 3; else >= 1).
  *                  Larger values trade restarts a little early for fewer float64
  *                  products, each of which costs a full sweep over the n^2 pairs.
+ *    block         0: every column its own PCG (the default).  1: block PCG
+ *                  (O'Leary): the nrhs right-hand sides of each lambda share one
+ *                  block Krylov space (nrhs <= 64, every right-hand side of a lambda
+ *                  non-zero); the lambdas share each kernel product.  Low-precision
+ *                  products refine whole blocks in cycles (refine_every must be 0;
+ *                  refine_mode and refine_join do not apply).  NYS_ENOTPD when a
+ *                  block loses rank twice in a row.
  */
 typedef struct {
   double tol;
@@ -210,6 +217,8 @@ typedef struct {
   int32_t max_refinements;
   double refine_reduction;
   double refine_join;
+  int32_t block;
+  int32_t reserved;
 } nys_pcg_opts;
 
 /* Per-column result. */

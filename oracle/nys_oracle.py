@@ -285,6 +285,47 @@ def pcg(apply_A, b: np.ndarray, apply_Pinv=None, tol: float = 1e-6, max_iters: i
     return x, it, rel
 
 
+def block_pcg(apply_A, B: np.ndarray, apply_Pinv=None, tol: float = 1e-6, max_iters: int = 1000):
+    """O'Leary's block preconditioned CG for A X = B with the s columns of B sharing one
+    block Krylov space (the block variant of the batched solve), x0 = 0.  Per iteration:
+    Q = A P, alpha = (P^T Q)^{-1} (R^T Z), X += P alpha, R -= Q alpha, Z = M^{-1} R,
+    beta = (R_old^T Z_old)^{-1} (R^T Z), P = Z + P beta, the s x s systems solved by
+    Cholesky.  Stops when every column has |r_c| <= tol |b_c| (the per right-hand-side
+    rule of table tab:rlaopt-pcg-stopping) or after max_iters products.  Returns
+    (X, iterations, per-column recursive relres); a Cholesky failure (the block lost
+    rank) raises numpy.linalg.LinAlgError."""
+    B = np.asarray(B, dtype=np.float64)
+    if B.ndim == 1:
+        B = B[:, None]
+    bn = np.linalg.norm(B, axis=0)
+    bn_safe = np.where(bn > 0, bn, 1.0)
+    X = np.zeros_like(B)
+    R = B.copy()
+    rel = np.linalg.norm(R, axis=0) / bn_safe
+    if np.all(rel <= tol):
+        return X, 0, rel
+    Z = apply_Pinv(R) if apply_Pinv is not None else R.copy()
+    P = Z.copy()
+    RZ = R.T @ Z
+    it = 0
+    while it < max_iters:
+        Q = apply_A(P)
+        G = P.T @ Q
+        alpha = sla.cho_solve(sla.cho_factor(0.5 * (G + G.T), lower=True), RZ)
+        X = X + P @ alpha
+        R = R - Q @ alpha
+        it += 1
+        rel = np.linalg.norm(R, axis=0) / bn_safe
+        if np.all(rel <= tol):
+            break
+        Z = apply_Pinv(R) if apply_Pinv is not None else R.copy()
+        RZn = R.T @ Z
+        beta = sla.cho_solve(sla.cho_factor(0.5 * (RZ + RZ.T), lower=True), RZn)
+        RZ = RZn
+        P = Z + P @ beta
+    return X, it, rel
+
+
 def nyspcg_dense(X, B, lambdas, kind, sigma, Omega=None, tol=1e-6, max_iters=1000):
     """NysPCG on every column: column c uses lambdas[c // nrhs] and B[:, c % nrhs].
     Omega None -> plain CG.  Returns (Xsol (n, nlam*nrhs), iters list, recursive relres list,

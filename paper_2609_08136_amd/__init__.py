@@ -56,7 +56,7 @@ class NysNystromConfig(ctypes.Structure):
 class NysPCGOpts(ctypes.Structure):
     _fields_ = [("tol", c_f64), ("max_iters", c_i32), ("prec", c_i32), ("refine_every", c_i32),
                 ("refine_mode", c_i32), ("check_true", c_i32), ("max_refinements", c_i32),
-                ("refine_reduction", c_f64), ("refine_join", c_f64)]
+                ("refine_reduction", c_f64), ("refine_join", c_f64), ("block", c_i32), ("reserved", c_i32)]
 
 
 class NysAdmmConfig(ctypes.Structure):
@@ -379,9 +379,9 @@ def nys_precond_apply(P: Preconditioner, lambdas, R, prec: int = FP64):
 
 
 def _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements,
-          refine_reduction=1e-3, refine_join=0.0) -> NysPCGOpts:
+          refine_reduction=1e-3, refine_join=0.0, block=False) -> NysPCGOpts:
     return NysPCGOpts(float(tol), int(max_iters), int(prec), int(refine_every), int(refine_mode), int(check_true),
-                      int(max_refinements), float(refine_reduction), float(refine_join))
+                      int(max_refinements), float(refine_reduction), float(refine_join), int(bool(block)), 0)
 
 
 def _info_list(arr, count):
@@ -392,9 +392,10 @@ def _info_list(arr, count):
 def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | None = None, tol: float = 1e-6,
                  max_iters: int = 1000, prec: int = FP64, refine_every: int = -1, refine_mode: int = 0,
                  check_true: bool = False, max_refinements: int = 0, workspace: torch.Tensor | None = None,
-                 refine_reduction: float = 1e-3, refine_join: float = 0.0):
+                 refine_reduction: float = 1e-3, refine_join: float = 0.0, block: bool = False):
     """Solve (K + lambdas[l] I) x = B[:, j] for every (l, j); column l*nrhs + j of the result.
-    Returns (Xsol (n x nlam*nrhs float64), info list, status)."""
+    block=True: block PCG, the right-hand sides of each lambda sharing one block Krylov
+    space.  Returns (Xsol (n x nlam*nrhs float64), info list, status)."""
     lib = load()
     _need_cuda(X, torch.float64, "X")
     vec = B.dim() == 1
@@ -411,7 +412,7 @@ def nyspcg_solve(X, B, lambdas, kind: int, sigma: float, P: Preconditioner | Non
     need = nys_workspace_bytes(OP_SOLVE, n, 0, d, P.r if P is not None else 0, m, prec)
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
     o = _opts(tol, max_iters, prec, refine_every, refine_mode, check_true, max_refinements, refine_reduction,
-              refine_join)
+              refine_join, block)
     cs = P.c_struct() if P is not None else None
     rc = lib.nyspcg_solve(NysKernel(kind, 0, float(sigma)), X.data_ptr(), n, d, B2.data_ptr(), nrhs, lam_arr, nlam,
                           ctypes.byref(cs) if cs is not None else None, ctypes.byref(o), Xsol.data_ptr(), info,

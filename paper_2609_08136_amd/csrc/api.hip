@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "admm.h"
+#include "block.h"
 #include "gemv.h"
 #include "pcg.h"
 
@@ -510,8 +511,9 @@ int32_t orth_test_matrix(const double *Omega, uint64_t seed, int64_t pd, int r, 
   return NYS_OK;
 }
 
-// The PCG driver (solve_columns).
+// The PCG driver (solve_columns) and its block variant (solve_blocks).
 #include "solve_impl.h"
+#include "block_impl.h"
 
 // The stabilised approximation from a sketch (Y, Q of r columns): fills P->U (n x r),
 // P->lam_hat, P->U32 (when given), P->rank and P->nu.
@@ -739,6 +741,7 @@ int32_t check_opts(const nys_pcg_opts *o) {
   if (o->refine_mode < 0 || o->refine_mode > 2) return einval("refine_mode must be 0, 1 or 2");
   if (!(o->refine_join == 0.0 || o->refine_join >= 1.0) || !std::isfinite(o->refine_join))
     return einval("refine_join must be 0 or >= 1");
+  if (o->block != 0 && o->block != 1) return einval("block must be 0 or 1");
   return NYS_OK;
 }
 
@@ -955,6 +958,8 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
     case NYS_OP_SOLVE: {
       SolvePlan p;
       plan_solve(p, std::max<int64_t>(n, 1), std::max(d, 1), r, std::max(m, 1), prec, true, true, a);
+      BlockPlan b;
+      plan_block(b, std::max<int64_t>(n, 1), std::max(m, 1), a);
       break;
     }
     case NYS_OP_BACKWARD: {
@@ -1275,6 +1280,18 @@ int32_t nyspcg_solve(nys_kernel k, const double *X, int64_t n, int32_t d, const 
   a.cap = ws_bytes;
   SolvePlan sp;
   plan_solve(sp, n, d, P ? P->r : 0, m, prec, opts->refine_every >= 0, opts->check_true != 0, a);
+  if (opts->block) {
+    if (nrhs > block_max_s()) return einval("block PCG takes at most 64 right-hand sides per lambda");
+    if (prec != NYS_FP64 && opts->refine_every != 0)
+      return einval("block PCG with a low-precision product refines in cycles (refine_every 0)");
+    BlockPlan bp;
+    plan_block(bp, n, m, a);
+    NYS_RETURN_IF(check_ws(a));
+    KernelOp op{k, X, d, sp};
+    if (prec == NYS_FP64)
+      return solve_blocks<double>(op, n, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, bp, s);
+    return solve_blocks<float>(op, n, B, nrhs, lambdas, nlam, P, *opts, Xsol, info, sp, bp, s);
+  }
   NYS_RETURN_IF(check_ws(a));
   KernelOp op{k, X, d, sp};
   if (prec == NYS_FP64)
@@ -1307,6 +1324,7 @@ int32_t nys_ridge_solve(const double *X, int64_t n, int64_t p, const double *Yt,
                         const double *lambdas, int32_t nlam, const nys_precond *P, const nys_pcg_opts *opts,
                         double *W, nys_col_info *info, void *ws, size_t ws_bytes, void *stream) {
   NYS_RETURN_IF(check_opts(opts));
+  if (opts->block) return einval("block PCG is offered by nyspcg_solve only");
   if (opts->prec != NYS_FP64) return einval("the ridge solve runs in float64 (prec NYS_FP64)");
   if (n < 1 || p < 1 || n > INT32_MAX || p > INT32_MAX) return einval("need 1 <= n, p < 2^31");
   if (nrhs < 1 || nlam < 1) return einval("nrhs and nlam must be >= 1");
@@ -1361,6 +1379,7 @@ int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, dou
                         size_t ws_bytes, void *stream) {
   NYS_RETURN_IF(check_kernel(k));
   NYS_RETURN_IF(check_opts(opts));
+  if (opts->block) return einval("block PCG is offered by nyspcg_solve only");
   const int prec = opts->prec;
   if (n < 1 || d < 1 || d > max_dim(NYS_FP64)) return einval("n >= 1 and 1 <= d <= 62 required");
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return einval("lambda must be > 0");

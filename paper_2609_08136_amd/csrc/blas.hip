@@ -107,6 +107,16 @@ int32_t gemm_tn_df(const double *A, int lda, const float *B, int ldb, int64_t n,
   return gemm_tn_impl<double, float, double>(A, lda, B, ldb, n, p, q, C, ldc, partial, splits, s);
 }
 
+template <class T>
+int32_t gemm_tn_to_double(const T *A, int lda, const T *B, int ldb, int64_t n, int p, int q, double *C, int ldc,
+                          double *partial, int splits, hipStream_t s) {
+  return gemm_tn_impl<T, T, double>(A, lda, B, ldb, n, p, q, C, ldc, partial, splits, s);
+}
+template int32_t gemm_tn_to_double<float>(const float *, int, const float *, int, int64_t, int, int, double *, int,
+                                          double *, int, hipStream_t);
+template int32_t gemm_tn_to_double<double>(const double *, int, const double *, int, int64_t, int, int, double *,
+                                           int, double *, int, hipStream_t);
+
 // --------------------------------------------------------------- C = A B (+ R * rscale)
 // Arithmetic in T; the output C and the epilogue operand R have type TC.
 template <class T, class TC>

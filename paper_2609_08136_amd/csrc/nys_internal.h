@@ -158,6 +158,10 @@ int gemm_tn_splits(int64_t n, int p, int q);
 // Mixed: C (double) = A^T B with A double and B float (products and sums in float64).
 int32_t gemm_tn_df(const double *A, int lda, const float *B, int ldb, int64_t n, int p, int q, double *C,
                    int ldc, double *partial, int splits, hipStream_t s);
+// C (double) = A^T B with A, B of type T (products in T, sums in float64).
+template <class T>
+int32_t gemm_tn_to_double(const T *A, int lda, const T *B, int ldb, int64_t n, int p, int q, double *C, int ldc,
+                          double *partial, int splits, hipStream_t s);
 // Mixed: C (float) = A B + R * rscale[col], arithmetic in float64, R float.
 int32_t gemm_nn_dd_f(const double *A, int lda, const double *B, int ldb, int64_t n, int p, int q, float *C,
                      int ldc, const float *R, int ldr, const double *rscale, hipStream_t s);

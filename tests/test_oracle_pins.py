@@ -647,3 +647,48 @@ def test_nysadmm_without_penalties_or_active_bounds_is_ridge():
     yc = pr.y - pr.y.mean()
     ref = np.linalg.solve(Xc.T @ Xc / 500 + lam2 * np.eye(30), Xc.T @ yc / 500)
     assert res["converged"] and np.max(np.abs(res["w"] - ref)) <= 1e-8
+
+
+# ---------------------------------------------------------------- block PCG (O'Leary)
+
+def test_block_pcg_with_one_column_is_pcg():
+    """A block of one column is textbook PCG: the same iterates and iteration count (on a
+    well-conditioned system, where the two roundings cannot steer the paths apart)."""
+    w = ni.small_problem(400, 5, seed=90, r=20)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(400, 20, 90))
+    lam = 1.0
+    A = lambda V: K @ V + lam * V
+    Pinv = lambda R: o.precond_apply(U, lh, lam, R)
+    b = w.B[:, 0]
+    Xb, itb, _ = o.block_pcg(A, b[:, None], Pinv, tol=1e-8)
+    x, it, _ = o.pcg(lambda v: A(v[:, None])[:, 0], b, lambda r: Pinv(r[:, None])[:, 0], tol=1e-8)
+    assert itb == it and np.max(np.abs(Xb[:, 0] - x)) <= 1e-12 * np.max(np.abs(x))
+
+
+def test_block_pcg_terminates_in_n_over_s_steps():
+    """In exact arithmetic block CG ends after at most ceil(n / s) block steps (the block
+    Krylov space fills R^n); on a small well-conditioned system it reaches the direct
+    solution within that count plus a few rounding steps, and far fewer than column CG."""
+    rng = np.random.default_rng(91)
+    n, s = 48, 6
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * np.linspace(1.0, 50.0, n)) @ Q.T
+    B = rng.standard_normal((n, s))
+    X, it, rel = o.block_pcg(lambda V: A @ V, B, None, tol=1e-11, max_iters=200)
+    assert it <= n // s + 2
+    assert np.max(np.abs(X - np.linalg.solve(A, B))) <= 1e-9 * np.max(np.abs(X))
+    its = [o.pcg(lambda v: A @ v, B[:, c], None, tol=1e-11, max_iters=200)[1] for c in range(s)]
+    assert it < min(its)
+
+
+def test_block_pcg_matches_direct_solves_on_a_kernel_system():
+    w = ni.small_problem(600, 6, seed=92, nrhs=8, r=30)
+    K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
+    U, lh, _ = o.nystrom(lambda V: K @ V, ni.gaussian_test_matrix(600, 30, 92))
+    lam = 1e-3
+    X, it, rel = o.block_pcg(lambda V: K @ V + lam * V, w.B, lambda R: o.precond_apply(U, lh, lam, R), tol=1e-10,
+                             max_iters=3000)
+    ref = np.linalg.solve(K + lam * np.eye(600), w.B)
+    assert np.all(rel <= 1e-10)
+    assert np.max(np.abs(X - ref)) <= 1e-6 * np.max(np.abs(ref))
