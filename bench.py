@@ -599,12 +599,15 @@ def headline(args):
     m = nrhs * nlam
     phase(f"inputs ready: n={n} d={d} r={r} columns={m} ({nrhs} rhs x {nlam} lambdas) prec={args.prec}")
 
-    t_tune, tiles = 0.0, None
+    t_tune, tiles, f64_tiles = 0.0, None, None
     if not args.no_autotune:
         t0 = time.perf_counter()
         tiles = nys.autotune(X, w.kind, w.sigma, prec, m, cache=args.tile_cache, n_rows=min(n, 262144))
+        # the float64 refinement products: per-chunk costs of every width on this shape
+        f64_tiles = nys.autotune_fp64_costs(X, w.kind, w.sigma, n_rows=min(n, 16384))
         t_tune = time.perf_counter() - t0
-        phase(f"autotune {t_tune:.1f} s: " + ", ".join(f"{k}: {v['tm']}" for k, v in tiles.items()))
+        phase(f"autotune {t_tune:.1f} s: " + ", ".join(f"{k}: {v['tm']}" for k, v in tiles.items())
+              + f"; float64 cost table measured, {f64_tiles['tm_at_256']} columns at 256")
     if args.kmv_only and args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
         dst = torch.empty_like(src)
@@ -748,7 +751,8 @@ def headline(args):
         "seeds": [rn["seed"] for rn in runs],
         "step_s": {"median": round(t_step, 3), "min": round(min(times), 3), "max": round(max(times), 3),
                    "all": [round(t, 3) for t in times]},
-        "tiles": {"autotune_s": round(t_tune, 1), "widths": {k: v["tm"] for k, v in (tiles or {}).items()}},
+        "tiles": {"autotune_s": round(t_tune, 1), "widths": {k: v["tm"] for k, v in (tiles or {}).items()},
+                  "fp64_cost_table": f64_tiles},
         "kernel_matvec_tflops": round(kmv_tflops, 1),
         "kernel_matvec": {"m": m, "ms": round(t_kmv * 1e3, 2), "tflops": round(kmv_tflops, 1),
                           "m1_ms": round(t_kmv1 * 1e3, 2),

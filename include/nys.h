@@ -401,8 +401,13 @@ int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, dou
  * d, 0, m, prec).  nys_set_tile installs a width (e.g. from a cache of earlier
  * runs; tm = 0 removes the range) and nys_clear_tiles drops every choice.
  * Valid widths: FP64 16, 32, 48, 64, 96, 128, 256 (without a tuned width its
- * planner takes the least measured cost); FP32 32, 64, 128; F16X3_D10 16..256 and
- * the other bf16 splits 32..256 in powers of two.  Whatever the width, the last
+ * planner takes the least cost over full chunks plus a tail chunk from a per-chunk
+ * cost table); FP32 32, 64, 128; F16X3_D10 16..256 and the other bf16 splits 32..256
+ * in powers of two.  For FP64 with m >= 256, nys_autotune instead times one chunk of
+ * every float64 width (m_lo is ignored) and replaces that cost table for this shape,
+ * so every later float64 product is sized by measured cost; best gets the width the
+ * planner then takes at m columns and its estimated milliseconds.  nys_clear_tiles
+ * restores the default table (measured at n = 1e6, d = 16).  Whatever the width, the last
  * chunk of a product runs at the narrowest width that holds the remaining
  * columns. */
 typedef struct {

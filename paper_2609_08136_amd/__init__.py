@@ -590,6 +590,16 @@ def nys_peak_probe(which: int, iters: int = 0, workspace: torch.Tensor | None = 
     return float(rate.value)
 
 
+def autotune_fp64_costs(X, kind: int, sigma: float, n_rows: int | None = None, reps: int = 1) -> dict:
+    """Measure the float64 product's per-chunk cost of every width on X[0:n_rows] x X
+    and install it as the float64 planner's cost table (the refinement residuals and
+    float64 solves then size every product by measured cost).  Returns the width the
+    planner takes at 256 columns and its estimated milliseconds."""
+    n_rows = X.shape[0] if n_rows is None else min(int(n_rows), X.shape[0])
+    tm, ms = nys_autotune(X, kind, sigma, FP64, 256, m_lo=1, n_rows=n_rows, reps=reps)
+    return {"tm_at_256": tm, "ms_at_256": ms, "n_rows": n_rows}
+
+
 def autotune(X, kind: int, sigma: float, prec: int, m_max: int, cache: str | None = None, reps: int = 1,
              n_rows: int | None = None) -> dict:
     """Tune every column-count bucket up to m_max (see TUNE_BUCKETS), timing rows

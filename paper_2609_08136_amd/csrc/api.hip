@@ -170,7 +170,7 @@ int32_t plan_autotune(AutotunePlan &p, int64_t n_rows, int64_t n, int d, int m, 
   if (base == 1) {
     int pw = 1;
     while (pw < m) pw *= 2;
-    for (int tm : {16, 32, 64, 128, 256})
+    for (int tm : {16, 32, 48, 64, 96, 128, 256})
       if (kmv_tile_valid(key, tm) && ceil_div(m, tm) <= 4 && tm <= 2 * std::max(pw, 16)) p.cands.push_back(tm);
   }
   const size_t eb = elem_bytes(prec);
@@ -1060,6 +1060,42 @@ int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int
   int best_tm = 0;
   int32_t rc = NYS_OK;
   const auto saved = kmv_tune_snapshot();
+  if (key == NYS_FP64 && m >= 256) {
+    // float64: time one chunk of every width and replace the planner's cost table,
+    // which then sizes every float64 product (mixed widths and tails) by least cost
+    static const int tms[7] = {16, 32, 48, 64, 96, 128, 256};
+    double cost[7];
+    for (int t = 0; t < 7 && rc == NYS_OK; ++t) {
+      kmv_tune_set(key, tms[t], tms[t], tms[t]);
+      rc = run_kmv(p.kv, k, 0, prec, 0, p.V, tms[t], m, p.Out, m, 1.0, 0.0, s);   // untimed first call
+      if (rc != NYS_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) { rc = NYS_EHIP; break; }
+      for (int q = 0; q < reps && rc == NYS_OK; ++q)
+        rc = run_kmv(p.kv, k, 0, prec, 0, p.V, tms[t], m, p.Out, m, 1.0, 0.0, s);
+      if (rc != NYS_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = NYS_EHIP;
+        break;
+      }
+      cost[t] = ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    kmv_tune_restore(saved);
+    if (rc != NYS_OK) {
+      if (rc == NYS_EHIP) set_error("nys_autotune: HIP event failure while timing");
+      return rc;
+    }
+    kmv_f64_cost_set(cost);
+    const KmvPlan kp = kmv_plan(n_rows, n, m, prec, p.kv.rows.Kp);
+    double est = 0.0;
+    for (int t = 0; t < 7; ++t)
+      if (tms[t] == kp.tm) est = cost[t] * (double)ceil_div(m, kp.tm);
+    *best = nys_tile_choice{kp.tm, 0, est};
+    return NYS_OK;
+  }
   for (int tm : p.cands) {
     kmv_tune_set(key, m, m, tm);
     rc = run_kmv(p.kv, k, 0, prec, 0, p.V, m, m, p.Out, m, 1.0, 0.0, s);   // untimed first call

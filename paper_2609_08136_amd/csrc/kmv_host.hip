@@ -337,9 +337,19 @@ void kmv_tune_set(int prec, int m_lo, int m_hi, int tm) {
   if (tm > 0) keep.push_back(Tuned{prec, m_lo, m_hi, tm});
   g_tuned.swap(keep);
 }
+// Per-chunk cost of each float64 width (seconds, relative values are what matter),
+// measured at n = 1e6, d = 16 until nys_autotune measures the shape at hand.
+constexpr int kF64Widths[7] = {16, 32, 48, 64, 96, 128, 256};
+constexpr double kF64CostDefault[7] = {1.57, 2.00, 2.50, 2.98, 3.94, 4.63, 8.55};
+double g_f64_cost[7] = {1.57, 2.00, 2.50, 2.98, 3.94, 4.63, 8.55};
+void kmv_f64_cost_set(const double *c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int t = 0; t < 7; ++t) g_f64_cost[t] = c[t];
+}
 void kmv_tune_clear() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned.clear();
+  for (int t = 0; t < 7; ++t) g_f64_cost[t] = kF64CostDefault[t];
 }
 std::vector<std::array<int, 4>> kmv_tune_snapshot() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -388,10 +398,14 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       p.r = 2;
     } else {
       // float64: the chunk width with the least cost over its full chunks plus the
-      // narrowest chunk that holds the remainder, the cost of one chunk measured at
-      // n = 1e6, d = 16 (seconds; every chunk recomputes the exponents)
-      static const int tms[] = {16, 32, 48, 64, 96, 128, 256};
-      static const double cost[] = {1.57, 2.00, 2.50, 2.98, 3.94, 4.63, 8.55};
+      // narrowest chunk that holds the remainder, from the per-chunk cost table (every
+      // chunk recomputes the exponents; nys_autotune re-measures the table)
+      const int *tms = kF64Widths;
+      double cost[7];
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int t = 0; t < 7; ++t) cost[t] = g_f64_cost[t];
+      }
       double best = 1e300;
       for (int t = 0; t < 7; ++t) {
         const int64_t full = ceil_div(m, tms[t]) - 1;

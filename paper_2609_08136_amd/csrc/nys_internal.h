@@ -144,7 +144,9 @@ int32_t kmv_run(const KmvPlan &plan, const nys_kernel &k, int deriv, int prec,
 // Autotuned chunk widths: tm for columns m in [m_lo, m_hi] of a precision (tm 0 removes).
 bool kmv_tile_valid(int prec, int tm);
 void kmv_tune_set(int prec, int m_lo, int m_hi, int tm);
-void kmv_tune_clear();
+void kmv_tune_clear();   // also restores the default float64 cost table
+// Replace the float64 planner's per-chunk costs of the widths 16, 32, 48, 64, 96, 128, 256.
+void kmv_f64_cost_set(const double *cost7);
 std::vector<std::array<int, 4>> kmv_tune_snapshot();
 void kmv_tune_restore(const std::vector<std::array<int, 4>> &t);
 

@@ -338,6 +338,32 @@ def test_autotune_records_a_valid_width(nys):
         nys.nys_clear_tiles()
 
 
+def test_fp64_cost_table_autotune(nys):
+    """The float64 cost-table tuning measures every width and replaces the planner's
+    table: the plans it then makes are valid widths, float64 products at in-between
+    widths still match the oracle, and clearing the tiles restores the default plans."""
+    rng = np.random.default_rng(6)
+    X = torch.from_numpy(rng.standard_normal((5000, 20))).to(torch.device("cuda"))
+    before = {m: nys.nys_plan_chunks(nys.FP64, 5000, 20, m) for m in (40, 96, 200, 300)}
+    try:
+        res = nys.autotune_fp64_costs(X, o.RBF, 4.5, n_rows=2048)
+        print("float64 cost tuning:", res)
+        assert res["tm_at_256"] in (16, 32, 48, 64, 96, 128, 256) and res["ms_at_256"] > 0
+        Xn = X.cpu().numpy()
+        for m in (40, 96, 200, 300):
+            tm, tail = nys.nys_plan_chunks(nys.FP64, 5000, 20, m)
+            assert tm in (16, 32, 48, 64, 96, 128, 256) and (tail == 0 or tail < tm)
+        V = rng.standard_normal((5000, 200))
+        got = run(nys, Xn, Xn, V, o.RBF, 4.5, 0)
+        ref = o.kernel_matvec(Xn, Xn, V, o.RBF, 4.5)
+        tol = kb.product_bound(Xn, Xn, V, o.RBF, 4.5, 0, same=True)
+        assert kb.guard(tol, ref) < GUARD
+        assert np.max(np.abs(got - ref) / tol) <= 1.0
+    finally:
+        nys.nys_clear_tiles()
+    assert {m: nys.nys_plan_chunks(nys.FP64, 5000, 20, m) for m in (40, 96, 200, 300)} == before
+
+
 @pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("where", ["rows", "cols", "inf"])
