@@ -204,8 +204,12 @@ typedef struct {
  *                  block Krylov space (nrhs <= 64, every right-hand side of a lambda
  *                  non-zero); the lambdas share each kernel product.  Low-precision
  *                  products refine whole blocks in cycles (refine_every must be 0;
- *                  refine_mode and refine_join do not apply).  NYS_ENOTPD when a
- *                  block loses rank twice in a row.
+ *                  refine_mode and refine_join do not apply; every refinement
+ *                  restarts the block).  A block's first cycle factor is raised to
+ *                  the drift (true - recursive relative residual) that the blocks
+ *                  already refined left at the end of their first cycle, scaled by
+ *                  their lambda over its lambda.  NYS_ENOTPD when a block loses rank
+ *                  twice in a row.
  */
 typedef struct {
   double tol;

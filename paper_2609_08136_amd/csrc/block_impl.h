@@ -16,7 +16,11 @@
 // lambda I) x64 is recomputed in float64 for the whole group, which is accepted when
 // every column's true residual meets tol, and otherwise restarts (P = Z).  A Cholesky
 // failure (the block lost rank) restarts the group the same way; two in a row end it
-// with NYS_ENOTPD.
+// with NYS_ENOTPD.  A later cycle's factor is the true-residual reduction the previous
+// one achieved (at least refine_reduction, at most 0.5).  The first cycle's factor is
+// at least kap1 / lambda, kap1 the largest first-cycle drift times lambda seen so far
+// (the drift of a cycle that starts from x = 0 scales as 1 / lambda), so a group whose
+// first cycle would stall on drift ends it where the drift is reached.
 #pragma once
 
 struct BlockPlan {
@@ -263,6 +267,15 @@ int32_t solve_blocks(Op &op, int64_t n, const double *B, int nrhs, const double 
   }
 
   std::vector<double> Gh, Ch;
+  // First-cycle drift constant: over the groups refined so far, the largest
+  // (true - recursive) relative residual at the end of their first cycle times their
+  // lambda.  The first cycle starts from x = 0, and its drift grows with the iterate,
+  // whose norm reaches |b| / lambda in the directions K barely damps, so the drift a
+  // first cycle accumulates scales as 1 / lambda.  Large lambdas converge first; a
+  // group still in its first cycle ends it once its recursive residual reaches the
+  // drift predicted for its lambda (iterating further lowers only the recursive
+  // residual).
+  double kap1 = 0.0;
   int iter = 0;
   bool breakdown = false;
   while (ga > 0) {
@@ -285,6 +298,10 @@ int32_t solve_blocks(Op &op, int64_t n, const double *B, int nrhs, const double 
           std::copy(beta.begin(), beta.end(), Ch.begin() + (size_t)q * S * S);
         } else {
           G.restart = true;       // beta = 0: P = Z
+          if (verbose) {
+            std::fprintf(stderr, "[nys] block iter %d lambda %.4g: R^T Z lost rank, P = Z\n", iter, G.lam);
+            std::fflush(stderr);
+          }
         }
       }
       G.RZ = RZn;
@@ -372,9 +389,18 @@ int32_t solve_blocks(Op &op, int64_t n, const double *B, int nrhs, const double 
         }
         continue;
       }
-      double thr = G.delta > 0.0 ? G.delta * G.rstart : tol;
+      double delta = G.delta;
+      if (delta > 0.0 && G.refs == 0 && kap1 > 0.0 && G.lam > 0.0) delta = std::max(delta, std::min(0.5, kap1 / G.lam));
+      double thr = delta > 0.0 ? delta * G.rstart : tol;
       if (G.delta > 0.0 && thr < 10.0 * 0.3 * tol) thr = 0.3 * tol;
-      if (worst <= thr || capped || isfailed[q]) refine_q.push_back(q);
+      if (worst <= thr || capped || isfailed[q]) {
+        refine_q.push_back(q);
+        if (verbose) {
+          std::fprintf(stderr, "[nys] block iter %d lambda %.4g (%d its): refine at recursive %.3e%s\n", iter,
+                       G.lam, G.iters, worst, isfailed[q] ? " (P^T W lost rank)" : (capped ? " (cap)" : ""));
+          std::fflush(stderr);
+        }
+      }
     }
     if (verbose && (iter % 10 == 0 || iter == 1)) {
       std::fprintf(stderr, "[nys] block iter %d groups %d relres [%.3e, %.3e]\n", iter, ga, lo, hi);
@@ -386,16 +412,24 @@ int32_t solve_blocks(Op &op, int64_t n, const double *B, int nrhs, const double 
       for (size_t t = 0; t < refine_q.size(); ++t) {
         const int q = refine_q[t];
         Group &G = gr[q];
+        const bool first = G.refs == 0;
         G.refs += 1;
-        double worst = 0.0;
+        double worst = 0.0, drift = 0.0;
         for (int j = 0; j < S; ++j) {
           const double r = rt[t * S + j];
           worst = std::max(worst, r);
+          drift = std::max(drift, r - rel[q * S + j]);
           nys_col_info &ci = info[G.g * S + j];
           ci.refinements = G.refs;
           ci.relres_true = r;
         }
         worst_all = std::max(worst_all, worst);
+        if (first && G.lam > 0.0) kap1 = std::max(kap1, drift / G.rstart * G.lam);
+        if (verbose) {
+          std::fprintf(stderr, "[nys] block iter %d lambda %.4g: true %.3e (cycle factor was %.3e)\n", iter, G.lam,
+                       worst, G.delta);
+          std::fflush(stderr);
+        }
         if (worst <= tol) {
           for (int j = 0; j < S; ++j) info[G.g * S + j].status = NYS_OK;
           done.push_back(q);

@@ -340,6 +340,9 @@ void kmv_tune_set(int prec, int m_lo, int m_hi, int tm) {
 // Per-chunk cost of each float64 width (seconds, relative values are what matter),
 // measured at n = 1e6, d = 16 until nys_autotune measures the shape at hand.
 constexpr int kF64Widths[7] = {16, 32, 48, 64, 96, 128, 256};
+// points per float32 accumulator range and the HBM the partial sums may take (kmv_plan)
+constexpr int64_t kAccPoints = 16384;
+constexpr size_t kMaxPartialBytes = size_t(32) << 30;
 constexpr double kF64CostDefault[7] = {1.57, 2.00, 2.50, 2.98, 3.94, 4.63, 8.55};
 double g_f64_cost[7] = {1.57, 2.00, 2.50, 2.98, 3.94, 4.63, 8.55};
 void kmv_f64_cost_set(const double *c) {
@@ -450,6 +453,20 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   // enough workgroups to fill 256 CUs several times over; each split keeps >= 8 tiles
   int64_t want = ceil_div(2048, ntiles * chunks);
   int64_t splits = std::max<int64_t>(1, std::min<int64_t>(want, njt / 8));
+  // Accumulation length of the float32 tiles.  One MFMA accumulator adds a tile's
+  // contribution per column tile, so its rounding error grows with the number of
+  // points it sums (5e-6 relative for the row sums of K at n = 1e6 in one range).  In a
+  // solve at small lambda that error, times an iterate of norm up to |b| / lambda,
+  // becomes the drift between the recursive and the true residual.  The points are
+  // therefore split into ranges of at most kAccPoints, each summed in float32 and the
+  // ranges added in float64 (split_reduce_kernel), as far as kMaxPartialBytes of
+  // partial sums allow.  float64 tiles accumulate in float64 and keep one range.
+  if (prec != NYS_FP64) {
+    const int64_t acc = ceil_div(njt, std::max<int64_t>(1, kAccPoints / TJ));
+    const int64_t cap = std::max<int64_t>(1, (int64_t)(kMaxPartialBytes / ((size_t)std::max<int64_t>(nr, 1) *
+                                                                           (size_t)std::max(m, 1) * 4)));
+    splits = std::max(splits, std::min(acc, cap));
+  }
   p.jsteps = (int)ceil_div(njt, splits);
   p.splits = (int)ceil_div(njt, p.jsteps);
   p.m_pad = p.path == 1 ? (int64_t)chunks * p.tm : 0;

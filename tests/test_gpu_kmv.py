@@ -265,6 +265,41 @@ def test_unit_vector_entries_every_width_n1e6(nys, prec, widths):
         nys.nys_clear_tiles()
 
 
+_ORACLE_CACHE = {}
+
+
+@pytest.mark.parametrize("prec", [5, 4, 1])
+def test_row_sums_accumulated_in_bounded_ranges_n1e6(nys, prec):
+    """Row sums K 1 of the full-size point set (n = 1e6, d = 16, sigma = 4) on 64
+    sampled rows against the oracle.  Every term is positive, so a float32 accumulator
+    grows with the sum and so does its rounding error: a sequential float32 sum of N
+    similar positive terms, each rounding uniform within u = 2^-24 of the partial sum,
+    has a relative RMS error of u sqrt(N) / 3, 3.5e-6 for N = 31250 column tiles of 32
+    points.  The low-precision products sum ranges of at most 16384 points in float32
+    and add the ranges in float64: u sqrt(512) / 3 / sqrt(62) = 6e-8 here, plus the
+    output rounding (2^-24) and the unbiased entry errors, which average out over 1e6
+    terms.  The bound, 5e-7 RMS and 2e-6 at worst, fails for one float32 range over
+    all points (measured 5.2e-6 RMS, 2.7e-5 at worst)."""
+    w = ni.batched_lambda_grid(0, n=1_000_000, nrhs=2, nlam=1)
+    X = w.X
+    n = X.shape[0]
+    dev = torch.device("cuda")
+    tX = torch.from_numpy(X).to(dev)
+    rows = np.sort(np.random.default_rng(41).choice(n, 64, replace=False))
+    if "rowsum" not in _ORACLE_CACHE:        # the same 64 oracle rows serve every precision
+        _ORACLE_CACHE["rowsum"] = o.kernel_matvec_rows(X[rows], X, np.ones(n), o.RBF, w.sigma)
+    ref = _ORACLE_CACHE["rowsum"]
+    print(f"case row sums n=1e6 prec={prec}", flush=True)
+    out = nys.kernel_matvec(tX, tX, torch.ones(n, dtype=torch.float32, device=dev), o.RBF, w.sigma, prec)
+    torch.cuda.synchronize()
+    got = out[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+    rel = (got - ref) / ref
+    rms = float(np.sqrt(np.mean(rel ** 2)))
+    print(f"  relative error RMS {rms:.3g}, max {np.max(np.abs(rel)):.3g}", flush=True)
+    assert rms <= 5e-7
+    assert np.max(np.abs(rel)) <= 2e-6
+
+
 def test_six_term_distance_is_more_accurate(nys):
     """BF16X3_D6 splits the distance operands into three bf16 parts.  Products with
     unit vectors return single kernel entries (no accumulation error), so the
