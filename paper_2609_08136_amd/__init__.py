@@ -18,9 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnys.so")
 
 RBF, LAPLACIAN = 0, 1
-FP64, FP32, BF16X3, BF16X3_D6, BF16X3_D10, F16X3_D10 = 0, 1, 2, 3, 4, 5
+FP64, FP32, BF16X3, BF16X3_D6, BF16X3_D10, F16X3_D10, F16X3_D6 = 0, 1, 2, 3, 4, 5, 6
 PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3", BF16X3_D6: "bf16x3_d6", BF16X3_D10: "bf16x3_d10",
-              F16X3_D10: "f16x3_d10"}
+              F16X3_D10: "f16x3_d10", F16X3_D6: "f16x3_d6"}
 PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
 
 OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5

@@ -35,11 +35,12 @@ int32_t einval(const std::string &m) {
   set_error(m);
   return NYS_EINVAL;
 }
-bool valid_prec(int p) { return p >= NYS_FP64 && p <= NYS_F16X3_D10; }
+bool valid_prec(int p) { return p >= NYS_FP64 && p <= NYS_F16X3_D6; }
 int max_dim(int prec) {
   switch (prec) {
     case NYS_BF16X3: return 82;
-    case NYS_BF16X3_D6: return 41;
+    case NYS_BF16X3_D6:
+    case NYS_F16X3_D6: return 41;
     case NYS_BF16X3_D10:
     case NYS_F16X3_D10: return 24;
     default: return 62;
@@ -164,7 +165,7 @@ void plan_matvec(MatvecPlan &p, int64_t nr, int64_t nc, int d, int m, int prec, 
 }
 
 int32_t plan_autotune(AutotunePlan &p, int64_t n_rows, int64_t n, int d, int m, int prec, Arena &ws) {
-  const int key = f16_product(prec) ? NYS_F16X3_D10 : kernel_prec(prec);
+  const int key = tile_key(prec);
   p.cands.clear();
   const int base = kmv_plan(n_rows, n, m, prec, packed_kp(d, prec)).path;
   if (base == 1) {
@@ -1011,7 +1012,7 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
 int32_t nys_set_tile(int32_t prec, int32_t m_lo, int32_t m_hi, int32_t tm) {
   if (!valid_prec(prec)) return einval("unsupported precision");
   if (m_lo < 1 || m_hi < m_lo) return einval("need 1 <= m_lo <= m_hi");
-  const int key = f16_product(prec) ? NYS_F16X3_D10 : kernel_prec(prec);
+  const int key = tile_key(prec);
   if (tm != 0 && !kmv_tile_valid(key, tm)) return einval("no tile of this width for this precision");
   kmv_tune_set(key, m_lo, m_hi, tm);
   return NYS_OK;
@@ -1048,7 +1049,7 @@ int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int
   NYS_RETURN_IF(check_ws(a));
   *best = nys_tile_choice{0, 0, 0.0};
   if (p.cands.empty()) return NYS_OK;   // the row-sum tile: nothing to choose
-  const int key = f16_product(prec) ? NYS_F16X3_D10 : kernel_prec(prec);
+  const int key = tile_key(prec);
   const size_t eb = elem_bytes(prec);
   if (eb == 8) NYS_RETURN_IF(launch_fill(reinterpret_cast<double *>(p.V), 1.0 / n, n * (int64_t)m, s));
   else NYS_RETURN_IF(launch_fill_f(reinterpret_cast<float *>(p.V), 1.0f / (float)n, n * (int64_t)m, s));

@@ -325,7 +325,8 @@ bool kmv_tile_valid(int prec, int tm) {
   switch (prec) {
     case NYS_FP64: return tm == 16 || tm == 32 || tm == 48 || tm == 64 || tm == 96 || tm == 128 || tm == 256;
     case NYS_FP32: return tm == 32 || tm == 64 || tm == 128;
-    case NYS_F16X3_D10: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
+    case NYS_F16X3_D10:
+    case NYS_F16X3_D6: return tm == 16 || tm == 32 || tm == 64 || tm == 128 || tm == 256;
     default: return tm == 32 || tm == 64 || tm == 128 || tm == 256;
   }
 }
@@ -423,7 +424,7 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
       }
       p.r = 2;
     }
-    const int tuned = kmv_tune_get(f16v ? NYS_F16X3_D10 : prec0, m);
+    const int tuned = kmv_tune_get(tile_key(prec0), m);
     if (tuned > 0) p.tm = tuned;
     // float64: 48-, 64- and 256-column chunks take one 16-row block per wave (four
     // waves per SIMD up to 64 columns; 256 columns within the register budget).
@@ -474,7 +475,7 @@ KmvPlan kmv_plan(int64_t nr, int64_t nc, int m, int prec, int Kp) {
   // second launch; every chunk recomputes the exponents, so a narrower one is cheaper)
   if (p.path == 1 && chunks > 1) {
     const int rem = m - (chunks - 1) * p.tm;
-    const int key = f16v ? NYS_F16X3_D10 : prec0;
+    const int key = tile_key(prec0);
     for (int t : {16, 32, 48, 64, 96, 128, 256}) {
       if (t >= p.tm) break;
       if (t >= rem && kmv_tile_valid(key, t)) {

@@ -87,15 +87,22 @@ struct Packed {
   int prec = 0;
 };
 
-// The tile kernels run BF16X3_D6, BF16X3_D10 and F16X3_D10 with the BF16X3
-// instantiations (the packing differs: six or ten distance terms instead of
-// three; F16X3_D10 also switches the K V product to fp16 parts).
+// The tile kernels run BF16X3_D6, BF16X3_D10, F16X3_D10 and F16X3_D6 with the BF16X3
+// instantiations (the packing differs: six or ten distance terms instead of three;
+// the F16X3 precisions also switch the K V product to fp16 parts).
 inline int kernel_prec(int prec) {
-  return (prec == NYS_BF16X3_D6 || prec == NYS_BF16X3_D10 || prec == NYS_F16X3_D10) ? NYS_BF16X3 : prec;
+  return (prec == NYS_BF16X3_D6 || prec == NYS_BF16X3_D10 || prec == NYS_F16X3_D10 || prec == NYS_F16X3_D6)
+             ? NYS_BF16X3
+             : prec;
 }
-inline bool f16_product(int prec) { return prec == NYS_F16X3_D10; }
-// the distance packing of a precision (F16X3_D10 packs as BF16X3_D10)
-inline int packing_prec(int prec) { return prec == NYS_F16X3_D10 ? NYS_BF16X3_D10 : prec; }
+inline bool f16_product(int prec) { return prec == NYS_F16X3_D10 || prec == NYS_F16X3_D6; }
+// the distance packing of a precision (the F16X3 precisions pack as their bf16 twins)
+inline int packing_prec(int prec) {
+  return prec == NYS_F16X3_D10 ? NYS_BF16X3_D10 : (prec == NYS_F16X3_D6 ? NYS_BF16X3_D6 : prec);
+}
+// key of the tile tables (valid and tuned widths): the fp16-product precisions have
+// their own, the other split precisions share BF16X3's
+inline int tile_key(int prec) { return f16_product(prec) ? prec : kernel_prec(prec); }
 
 int packed_kp(int d, int prec);
 size_t packed_elem_bytes(int prec);

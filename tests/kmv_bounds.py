@@ -34,9 +34,9 @@ import numpy as np
 import oracle as o
 
 # unit roundoff of the exponent chain (split distance products, float32 accumulation)
-UDIST = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -16, 3: 2.0 ** -23, 4: 2.0 ** -24, 5: 2.0 ** -24}
+UDIST = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -16, 3: 2.0 ** -23, 4: 2.0 ** -24, 5: 2.0 ** -24, 6: 2.0 ** -23}
 # relative error of one split operand of the K V product
-USPLIT = {2: 2.0 ** -16, 3: 2.0 ** -16, 4: 2.0 ** -16, 5: 2.0 ** -22}
+USPLIT = {2: 2.0 ** -16, 3: 2.0 ** -16, 4: 2.0 ** -16, 5: 2.0 ** -22, 6: 2.0 ** -22}
 
 
 def uacc(prec):
@@ -50,7 +50,7 @@ def uexp(prec):
 def split_product(prec, m, deriv):
     if deriv:
         return False
-    return prec == 5 or (prec in (2, 3, 4) and m > 16)
+    return prec in (5, 6) or (prec in (2, 3, 4) and m > 16)
 
 
 def entry_abs_bound(Xr, Xc, kind, sigma, prec, m, deriv=0, same=None, mu=None):

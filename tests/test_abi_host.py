@@ -76,6 +76,7 @@ def test_kernel_matvec_argument_errors(lib):
     assert args(k, d=42, prec=nys.BF16X3_D6) == nys.EINVAL
     assert args(k, d=25, prec=nys.BF16X3_D10) == nys.EINVAL
     assert args(k, d=25, prec=nys.F16X3_D10) == nys.EINVAL
+    assert args(k, d=42, prec=nys.F16X3_D6) == nys.EINVAL
     assert args(k, deriv=2) == nys.EINVAL
     assert b"deriv" in lib.nys_last_error()
     # null workspace
@@ -94,7 +95,7 @@ def test_solve_argument_errors(lib):
     assert solve([-1.0]) == nys.EINVAL
     assert solve([float("nan")]) == nys.EINVAL
     assert solve([1.0], tol=0.0) == nys.EINVAL
-    assert solve([1.0], prec=6) == nys.EINVAL
+    assert solve([1.0], prec=7) == nys.EINVAL
     assert solve([1.0], mode=3) == nys.EINVAL
     assert solve([1.0], join=0.5) == nys.EINVAL     # a join window below the due point
     assert solve([1.0], join=float("inf")) == nys.EINVAL
@@ -185,6 +186,8 @@ def test_plan_chunks_last_chunk_and_float64_costs(lib):
     assert nys.nys_plan_chunks(nys.F16X3_D10, n, d, 320) == (256, 64)
     assert nys.nys_plan_chunks(nys.F16X3_D10, n, d, 270) == (256, 16)
     assert nys.nys_plan_chunks(nys.F16X3_D10, n, d, 1) == (16, 0)      # fp16 tile at every width
+    for m, want in ((512, (256, 0)), (320, (256, 64)), (270, (256, 16)), (1, (16, 0))):
+        assert nys.nys_plan_chunks(nys.F16X3_D6, n, d, m) == want        # the same tiles
     # float32: 128-column chunks, tail from its widths (32, 64, 128)
     assert nys.nys_plan_chunks(nys.FP32, n, d, 300) == (128, 64)
     assert nys.nys_plan_chunks(nys.FP32, n, d, 260) == (128, 32)
@@ -199,7 +202,7 @@ def test_plan_chunks_last_chunk_and_float64_costs(lib):
     assert nys.nys_plan_chunks(nys.FP64, n, d, 384) == (256, 128)
     assert nys.nys_plan_chunks(nys.FP64, n, d, 512) == (256, 0)
     # every plan's widths are tiles of that precision, and the chunks cover m
-    for prec in (nys.FP64, nys.FP32, nys.BF16X3, nys.F16X3_D10):
+    for prec in (nys.FP64, nys.FP32, nys.BF16X3, nys.F16X3_D10, nys.F16X3_D6):
         for m in range(1, 600, 7):
             tm, tail = nys.nys_plan_chunks(prec, n, d, m)
             if tm == 0:
@@ -214,6 +217,14 @@ def test_plan_chunks_follow_tuned_widths_and_reject_bad_arguments(lib):
     try:
         nys.nys_set_tile(nys.F16X3_D10, 257, 512, 128)
         assert nys.nys_plan_chunks(nys.F16X3_D10, 10**6, 16, 300) == (128, 64)
+        assert nys.nys_plan_chunks(nys.F16X3_D6, 10**6, 16, 300) == (256, 64)    # a table of its own
+        nys.nys_set_tile(nys.F16X3_D6, 257, 512, 128)
+        assert nys.nys_plan_chunks(nys.F16X3_D6, 10**6, 16, 300) == (128, 64)
+        # the bf16-split precisions share one table: a width tuned for BF16X3_D6 applies
+        # to its own plans (and to BF16X3's and BF16X3_D10's)
+        nys.nys_set_tile(nys.BF16X3_D6, 257, 512, 128)
+        for prec in (nys.BF16X3_D6, nys.BF16X3, nys.BF16X3_D10):
+            assert nys.nys_plan_chunks(prec, 10**6, 16, 300) == (128, 64)
     finally:
         nys.nys_clear_tiles()
     tm, tail = ctypes.c_int32(), ctypes.c_int32()

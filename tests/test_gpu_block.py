@@ -58,9 +58,9 @@ def test_fp64_block_pcg_matches_oracle(nys, kind):
             assert c["relres_true"] <= 10 * tol
 
 
-@pytest.mark.parametrize("prec", [1, 5])
+@pytest.mark.parametrize("prec", [1, 5, 6])
 def test_low_precision_block_pcg_reaches_true_tolerance(nys, prec):
-    """Float32 vectors with the FP32 or F16X3_D10 product, block refinement cycles: every
+    """Float32 vectors with the FP32, F16X3_D10 or F16X3_D6 product, block refinement cycles: every
     column's dense float64 oracle residual meets 1e-6 and equals the reported one."""
     n, nrhs, lams = 4000, 16, [1e-7 * 4000, 1e-5 * 4000, 1e-3 * 4000]
     w = ni.batched_lambda_grid(7, n=n, nrhs=nrhs, nlam=3, r=100)

@@ -64,7 +64,7 @@ def check(nys, n_r, n_c, d, m, kind, prec, seed=0, same=True, deriv=0, heavy=Fal
     return got, ref
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("n,d,m", [(1, 3, 1), (31, 10, 1), (257, 16, 3), (2000, 10, 1), (700, 20, 8),
                                    (513, 33, 16), (300, 1, 5)])
@@ -72,7 +72,7 @@ def test_matvec_small_m(nys, prec, kind, n, d, m):
     check(nys, n, n, d, m, kind, prec, seed=n + d + m)
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("n,d,m", [(100, 10, 17), (1000, 16, 64), (777, 20, 50), (1500, 32, 200),
                                    (2000, 10, 300), (600, 13, 24), (500, 5, 40)])
@@ -106,7 +106,7 @@ def test_fp64_kernel_entries_over_the_whole_exponent_range(nys, kind, m):
     assert ref.min() == 0.0 and np.all(got[ref == 0.0] <= 1e-300) and got.min() >= 0.0
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 5])
+@pytest.mark.parametrize("prec", [0, 1, 2, 5, 6])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("m", [1, 40])
 def test_matvec_duplicate_points(nys, prec, kind, m):
@@ -204,7 +204,8 @@ def test_matvec_large_sampled_rows(nys):
     rows = np.sort(rng.choice(X.shape[0], 24, replace=False))
     trows = torch.from_numpy(rows).to(dev)
     Vs = {}
-    for m, prec in ((1, 2), (512, 2), (256, 3), (128, 4), (64, 4), (512, 5), (40, 5), (1, 5), (1, 0), (64, 0)):
+    for m, prec in ((1, 2), (512, 2), (256, 3), (128, 4), (64, 4), (512, 5), (40, 5), (1, 5), (512, 6), (64, 6),
+                    (1, 6), (1, 0), (64, 0)):
         if m not in Vs:
             Vs[m] = rng.standard_normal((X.shape[0], m)).astype(np.float32).astype(np.float64)
         V = Vs[m]
@@ -224,7 +225,8 @@ def test_matvec_large_sampled_rows(nys):
             del out, tV
 
 
-@pytest.mark.parametrize("prec,widths", [(5, (16, 32, 64, 128, 256)), (2, (32, 256)), (0, (16, 128, 256))])
+@pytest.mark.parametrize("prec,widths", [(5, (16, 32, 64, 128, 256)), (6, (16, 64, 256)), (2, (32, 256)),
+                                         (0, (16, 128, 256))])
 def test_unit_vector_entries_every_width_n1e6(nys, prec, widths):
     """Single kernel entries of the full-size point set (n = 1e6, d = 16, sigma = 4)
     through every column-chunk width: V holds unit vectors e_j, so each output is one
@@ -268,7 +270,7 @@ def test_unit_vector_entries_every_width_n1e6(nys, prec, widths):
 _ORACLE_CACHE = {}
 
 
-@pytest.mark.parametrize("prec", [5, 4, 1])
+@pytest.mark.parametrize("prec", [6, 5, 4, 1])
 def test_row_sums_accumulated_in_bounded_ranges_n1e6(nys, prec):
     """Row sums K 1 of the full-size point set (n = 1e6, d = 16, sigma = 4) on 64
     sampled rows against the oracle.  Every term is positive, so a float32 accumulator
@@ -337,7 +339,7 @@ def test_fp16_product_is_more_accurate(nys):
 
 
 @pytest.mark.parametrize("prec,widths", [(0, (16, 32, 48, 64, 96, 128, 256)), (1, (32, 64, 128)), (2, (32, 64, 128, 256)),
-                                         (5, (16, 32, 64, 128, 256))])
+                                         (5, (16, 32, 64, 128, 256)), (6, (16, 32, 64, 128, 256))])
 def test_every_chunk_width_matches_oracle(nys, prec, widths):
     """Every column-chunk width the autotuner may choose gives the same products (to
     the precision's bound): each is forced for all column counts in turn."""
@@ -399,7 +401,7 @@ def test_fp64_cost_table_autotune(nys):
     assert {m: nys.nys_plan_chunks(nys.FP64, 5000, 20, m) for m in (40, 96, 200, 300)} == before
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("kind", [o.RBF, o.LAPLACIAN])
 @pytest.mark.parametrize("where", ["rows", "cols", "inf"])
 def test_non_finite_points_are_rejected(nys, prec, kind, where):

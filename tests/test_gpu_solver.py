@@ -60,7 +60,7 @@ def test_precond_low_precision_sketch_is_valid(nys):
     Om = ni.gaussian_test_matrix(w.n, w.r, 3)
     K = o.kernel_matrix(w.X, w.X, w.kind, w.sigma)
     _, lho, _ = o.nystrom(lambda V: K @ V, Om)
-    for prec in (1, 2, 3, 4, 5):
+    for prec in (1, 2, 3, 4, 5, 6):
         _, P = build(nys, w.X, Om, w.kind, w.sigma, prec)
         lh = P.lam_hat.cpu().numpy()
         U = P.U.cpu().numpy()
@@ -152,7 +152,7 @@ def test_nan_rhs_is_reported(nys):
 
 
 @pytest.mark.parametrize("prec,mode,every", [(1, 0, 20), (2, 0, 20), (2, 1, 20), (5, 1, 20), (5, 1, 0),
-                                              (5, 2, 0), (3, 0, 0)])
+                                              (5, 2, 0), (3, 0, 0), (6, 1, 0)])
 def test_low_precision_with_fp64_refinement_reaches_true_tolerance(nys, prec, mode, every):
     """Low-precision products (FP32, BF16X3, D6, F16X3_D10) with float32 CG accept a
     column only on its float64 true residual, with periodic (every 20) or cycle
@@ -278,10 +278,11 @@ def test_backward_low_precision_adjoint(nys):
 
 
 @pytest.mark.parametrize("prec,n,nrhs,lam_lo,lam_hi,r", [(5, 10_000, 64, 1e-7, 1e-3, 500),
+                                                          (6, 10_000, 64, 1e-7, 1e-3, 500),
                                                           (2, 4_000, 40, 1e-5, 1e-1, 200)])
 def test_headline_column_count_matches_oracle(nys, prec, n, nrhs, lam_lo, lam_hi, r):
     """The batched workload's recipe at the headline's column count: nrhs sign labels x
-    8 lambdas log-spaced over [lam_lo n, lam_hi n] (512 columns for F16X3_D10, 320 for
+    8 lambdas log-spaced over [lam_lo n, lam_hi n] (512 columns for F16X3_D10 and D6, 320 for
     BF16X3, whose three-term distance needs lambda above ~1e-5 n).  The solve runs its
     256-column chunks with narrower last chunks, compacts the active columns as they
     converge across widths, and batches float64 refinements of 48 to 256 columns.
@@ -320,7 +321,7 @@ def test_non_finite_points_in_solve_and_sketch(nys):
     with pytest.raises(nys.NysError) as ei:
         nys.build_preconditioner(tX, T(ni.gaussian_test_matrix(w.n, w.r, 2)), w.kind, w.sigma, 0)
     assert ei.value.code == nys.ENUMERIC
-    for prec in (0, 5):
+    for prec in (0, 5, 6):
         with pytest.raises(nys.NysError) as ei:
             nys.nyspcg_solve(tX, T(w.B), w.lambdas, w.kind, w.sigma, None, tol=1e-8, prec=prec,
                              refine_every=0)
