@@ -538,9 +538,11 @@ __global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, T
         }
       }
     // diagonal tiles (a wave-uniform test) pin the exponent of i == j to 0.  Hoisting the
-    // test out of the epilogue measured 5-6% faster at 64 and 256 columns, 2.6% slower
-    // at 128 and neutral below; those widths keep the per-element select.
-    constexpr bool HOIST = TM == 64 || TM == 256;
+    // test out of the epilogue measured 5-6% faster at 64 and 256 columns for the bf16
+    // product and 6.7% faster at 128 for the fp16 product over the six-term distance
+    // (whose narrow tiles are VALU-bound); the bf16 tiles of 128 columns and below keep
+    // the per-element select (2.6% faster at 128 when measured).
+    constexpr bool HOIST = F16V || TM == 64 || TM == 256;
     if (HOIST && diag) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -555,23 +557,56 @@ __global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, T
         }
       }
     }
+    // K split into hi and lo parts (k - hi is exact in float32).  The fp16 product of up
+    // to 128 columns converts the entries in pairs, one v_cvt_pk_f16_f32 per pair for
+    // the hi parts, so that each hi part is converted once; chunks up to 64 columns form
+    // the lo part as an fma with a half operand (v_fma_mix), 128-column ones by
+    // converting the hi pair back and subtracting.  Measured at n = 1e6 (one box, six-
+    // term distance): 1 column 317 -> 292 ms, 32 columns 389 -> 357 ms, 128 columns 838
+    // -> 767 ms; the 256-column tile measured 5% slower with pairs (2524 -> 2651 ms) and
+    // keeps one conversion per entry.
     PV phi[R], plo[R];
+    if constexpr (F16V && TM <= 128) {
+      typedef float f2v __attribute__((ext_vector_type(2)));
+      typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+      for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        float t = e < 4 ? ta[r][e] : tb[r][e - 4];
-        if constexpr (!HOIST) {
-          const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
-          if (diag && iw + r * 16 + col16 == gj) t = 0.0f;
+        for (int e = 0; e < 8; e += 2) {
+          const float k0 = kernel_value<NYS_BF16X3, KIND, 0>(e < 4 ? ta[r][e] : tb[r][e - 4], cL, dcoef);
+          const float k1 = kernel_value<NYS_BF16X3, KIND, 0>(e < 4 ? ta[r][e + 1] : tb[r][e - 3], cL, dcoef);
+          const h2v hp = __builtin_convertvector((f2v){k0, k1}, h2v);
+          phi[r][e] = hp[0];
+          phi[r][e + 1] = hp[1];
+          if constexpr (TM <= 64) {
+            plo[r][e] = (PS)__builtin_fmaf((float)hp[0], mone, k0);
+            plo[r][e + 1] = (PS)__builtin_fmaf((float)hp[1], mone, k1);
+          } else {
+            const f2v hf = __builtin_convertvector(hp, f2v);
+            const h2v lp = __builtin_convertvector((f2v){k0 - hf[0], k1 - hf[1]}, h2v);
+            plo[r][e] = lp[0];
+            plo[r][e + 1] = lp[1];
+          }
         }
-        const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);
-        const PS h = (PS)kv;
-        phi[r][e] = h;
-        // kv - h is exact in float32.  For the fp16 split, as one fma with a half
-        // operand it becomes a single v_fma_mix{lo,hi}_f16
-        if constexpr (F16V && TM <= 64) plo[r][e] = (PS)__builtin_fmaf((float)h, mone, kv);
-        else plo[r][e] = (PS)(kv - (float)h);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          float t = e < 4 ? ta[r][e] : tb[r][e - 4];
+          if constexpr (!HOIST) {
+            const int64_t gj = j0 + (e < 4 ? 4 * grp + e : 16 + 4 * grp + (e - 4));
+            if (diag && iw + r * 16 + col16 == gj) t = 0.0f;
+          }
+          const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);
+          const PS h = (PS)kv;
+          phi[r][e] = h;
+          // kv - h is exact in float32.  For the fp16 split, as one fma with a half
+          // operand it becomes a single v_fma_mix{lo,hi}_f16
+          if constexpr (F16V && TM <= 64) plo[r][e] = (PS)__builtin_fmaf((float)h, mone, kv);
+          else plo[r][e] = (PS)(kv - (float)h);
+        }
       }
     }
     // V operands are read one column block ahead of the MFMAs that use them
