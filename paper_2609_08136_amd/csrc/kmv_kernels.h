@@ -451,9 +451,8 @@ __global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, T
 
   const float cL = (float)a.cL, dcoef = (float)a.dcoef;
   // -1 kept opaque to the optimiser, so that kv - h stays an fma with a half operand
-  // (chunks up to 64 columns; the wider tiles measured faster with the plain form)
   float mone = -1.0f;
-  if constexpr (F16V && TM <= 64) asm volatile("" : "+v"(mone));
+  if constexpr (F16V) asm volatile("" : "+v"(mone));
   const int64_t njt = (a.nc + TJ - 1) / TJ;
   const int64_t jt0 = (int64_t)split * a.jsteps;
   const int64_t jt1 = jt0 + a.jsteps < njt ? jt0 + a.jsteps : njt;
@@ -557,16 +556,16 @@ __global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, T
         }
       }
     }
-    // K split into hi and lo parts (k - hi is exact in float32).  The fp16 product of up
-    // to 128 columns converts the entries in pairs, one v_cvt_pk_f16_f32 per pair for
-    // the hi parts, so that each hi part is converted once; chunks up to 64 columns form
-    // the lo part as an fma with a half operand (v_fma_mix), 128-column ones by
-    // converting the hi pair back and subtracting.  Measured at n = 1e6 (one box, six-
-    // term distance): 1 column 317 -> 292 ms, 32 columns 389 -> 357 ms, 128 columns 838
-    // -> 767 ms; the 256-column tile measured 5% slower with pairs (2524 -> 2651 ms) and
-    // keeps one conversion per entry.
+    // K split into hi and lo parts (k - hi is exact in float32).  The fp16 product
+    // converts the entries in pairs, one v_cvt_pk_f16_f32 per pair for the hi parts, so
+    // that each hi part is converted once, and forms the lo part as an fma with a half
+    // operand (v_fma_mix); the 128-column tile converts the hi pair back and subtracts
+    // instead.  Measured at n = 1e6 (one box per pair of runs, six-term distance): 1
+    // column 317 -> 292 ms, 32 columns 389 -> 357 ms, 128 columns 838 -> 767 ms, 512
+    // columns (two 256-column chunks) 2545 -> 2479 ms; the 256-column tile with the
+    // subtracting form measured 5% slower (2524 -> 2651 ms).
     PV phi[R], plo[R];
-    if constexpr (F16V && TM <= 128) {
+    if constexpr (F16V) {
       typedef float f2v __attribute__((ext_vector_type(2)));
       typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 #pragma unroll
@@ -578,7 +577,7 @@ __global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, T
           const h2v hp = __builtin_convertvector((f2v){k0, k1}, h2v);
           phi[r][e] = hp[0];
           phi[r][e + 1] = hp[1];
-          if constexpr (TM <= 64) {
+          if constexpr (TM != 128) {
             plo[r][e] = (PS)__builtin_fmaf((float)hp[0], mone, k0);
             plo[r][e + 1] = (PS)__builtin_fmaf((float)hp[1], mone, k1);
           } else {
@@ -602,10 +601,7 @@ __global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, T
           const float kv = kernel_value<NYS_BF16X3, KIND, 0>(t, cL, dcoef);
           const PS h = (PS)kv;
           phi[r][e] = h;
-          // kv - h is exact in float32.  For the fp16 split, as one fma with a half
-          // operand it becomes a single v_fma_mix{lo,hi}_f16
-          if constexpr (F16V && TM <= 64) plo[r][e] = (PS)__builtin_fmaf((float)h, mone, kv);
-          else plo[r][e] = (PS)(kv - (float)h);
+          plo[r][e] = (PS)(kv - (float)h);
         }
       }
     }
