@@ -445,7 +445,7 @@ def cpu_model() -> str:
 
 
 # Kernel sources whose hash a committed HBM-counter summary must match to be reported.
-KERNEL_SOURCES = ["kmv_common.h", "kmv_kernels.h", "kmv_host.hip", "kmv_bf16.hip", "kmv_f16.hip"]
+KERNEL_SOURCES = ["kmv_common.h", "kmv_kernels.h", "kmv_host.hip", "gen_dispatch.py"]
 
 
 def device_label(torch) -> str:
