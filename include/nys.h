@@ -273,10 +273,13 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
  *    V    device nc x m, float64 if prec == NYS_FP64 else float32
  *    Out  device nr x m, same type as V; not read when beta == 0
  * Coordinates are centred on the column mean of Xc (distances are unchanged).
- * d must be <= 62 (FP32/FP64), <= 82 (BF16X3), <= 41 (BF16X3_D6) or <= 24 (the
- * ten-term splits).  The stream is synchronised once, after the points are packed
- * and before the product is enqueued, to read the packing's finiteness check: a NaN
- * or Inf coordinate in Xr or Xc returns NYS_ENUMERIC. */
+ * d must be <= 62 (FP32/FP64), <= 82 (BF16X3), <= 41 (BF16X3_D6, F16X3_D6) or <= 24
+ * (the ten-term splits).  The low-precision products sum the columns' contributions
+ * in float32 over ranges of at most 16384 column points and add the ranges in
+ * float64 (the workspace holds the range sums, up to 32 GiB), so the rounding of one
+ * output does not grow with nc.  The stream is synchronised once, after the points
+ * are packed and before the product is enqueued, to read the packing's finiteness
+ * check: a NaN or Inf coordinate in Xr or Xc returns NYS_ENUMERIC. */
 int32_t kernel_matvec(nys_kernel k, int32_t deriv, int32_t prec,
                       const double *Xr, int64_t nr, const double *Xc, int64_t nc, int32_t d,
                       const void *V, int32_t m, void *Out, double alpha, double beta,
@@ -415,8 +418,9 @@ int32_t nyspcg_backward(nys_kernel k, const double *X, int64_t n, int32_t d, dou
  * runs; tm = 0 removes the range) and nys_clear_tiles drops every choice.
  * Valid widths: FP64 16, 32, 48, 64, 96, 128, 256 (without a tuned width its
  * planner takes the least cost over full chunks plus a tail chunk from a per-chunk
- * cost table); FP32 32, 64, 128; F16X3_D10 16..256 and the other bf16 splits 32..256
- * in powers of two.  For FP64 with m >= 256, nys_autotune instead times one chunk of
+ * cost table); FP32 32, 64, 128; F16X3_D10 and F16X3_D6 16..256 (each its own table)
+ * and the bf16 splits 32..256 (one table shared by BF16X3, D6 and D10), in powers of
+ * two.  For FP64 with m >= 256, nys_autotune instead times one chunk of
  * every float64 width (m_lo is ignored) and replaces that cost table for this shape,
  * so every later float64 product is sized by measured cost; best gets the width the
  * planner then takes at m columns and its estimated milliseconds.  nys_clear_tiles
