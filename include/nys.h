@@ -275,9 +275,10 @@ int32_t nys_workspace_bytes(int32_t op, int64_t n, int64_t n2, int32_t d, int32_
  * Coordinates are centred on the column mean of Xc (distances are unchanged).
  * d must be <= 62 (FP32/FP64), <= 82 (BF16X3), <= 41 (BF16X3_D6, F16X3_D6) or <= 24
  * (the ten-term splits).  The low-precision products sum the columns' contributions
- * in float32 over ranges of at most 16384 column points and add the ranges in
- * float64 (the workspace holds the range sums, up to 32 GiB), so the rounding of one
- * output does not grow with nc.  The stream is synchronised once, after the points
+ * in float32 over ranges of column points and add the ranges in float64: ranges of
+ * at most 16384 points where the range sums fit in 32 GiB of workspace, fewer and
+ * longer ranges where they would not (n = 1e6: 62 ranges up to 128 columns, 16 at
+ * 512), so the float32 rounding of an output grows with the range, not with nc.  The stream is synchronised once, after the points
  * are packed and before the product is enqueued, to read the packing's finiteness
  * check: a NaN or Inf coordinate in Xr or Xc returns NYS_ENUMERIC. */
 int32_t kernel_matvec(nys_kernel k, int32_t deriv, int32_t prec,
