@@ -390,13 +390,16 @@ template <> struct ProdType<true> { using V = h8; using S = _Float16; };
 
 // The 16- and (RBF) 32-column tiles run four waves per SIMD (two workgroups per CU)
 // within 128 registers; the 32-column one spills a few registers there and is still
-// faster (517 against 570 ms at n = 1e6, 32 columns).
-template <int KIND, int KSMAX, int TM>
+// faster (517 against 570 ms at n = 1e6, 32 columns).  So does the 64-column fp16 tile
+// over at most four K-steps (the six-term distance at d = 16): 5 registers spilled,
+// 459 against 519 ms at n = 1e6 (one box); over six K-steps it spilled 43 and ran
+// slower (780 against 635 ms).
+template <int KIND, int KSMAX, int TM, bool F16V>
 constexpr int flash2_waves_per_simd() {
-  return KSMAX <= 6 && (TM == 16 || (TM == 32 && KIND == NYS_RBF)) ? 4 : 2;
+  return (KSMAX <= 6 && (TM == 16 || (TM == 32 && KIND == NYS_RBF))) || (F16V && KSMAX <= 4 && TM == 64) ? 4 : 2;
 }
 template <int KIND, int KSMAX, int TM, bool F16V = false>
-__global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, TM>())) void kmv_flash2_kernel(KArgs a) {
+__global__ __launch_bounds__(KMV2_THREADS, (flash2_waves_per_simd<KIND, KSMAX, TM, F16V>())) void kmv_flash2_kernel(KArgs a) {
   using T = Tr<NYS_BF16X3>;
   using Op = typename T::Op;
   using PV = typename ProdType<F16V>::V;   // operand vector of the K V product
