@@ -131,6 +131,25 @@ def test_precond_apply_argument_errors(lib):
     assert lib.nys_precond_apply(ctypes.byref(bad), FAKE, nys.FP64, FAKE, 1, other, FAKE, 1 << 20, None) == nys.EINVAL
 
 
+def test_build_generates_the_dispatch_sources(tmp_path):
+    """The tile instantiations and their dispatch are generated at build time: the
+    generator writes one source per precision family, each defining its dispatch
+    function, none of them is kept under csrc/, and the build compiles them beside the
+    hand-written sources."""
+    from paper_2609_08136_amd import build
+    gen = build.gen_dispatch
+    paths = gen.write_all(str(tmp_path))
+    assert [os.path.basename(p) for p in paths] == gen.GENERATED
+    for p in paths:
+        name = os.path.splitext(os.path.basename(p))[0].replace("kmv_", "")
+        text = open(p).read()
+        assert f"int32_t kmv_dispatch_{name}(" in text and "hipLaunchKernelGGL" in text
+    csrc = os.path.join(ROOT, "paper_2609_08136_amd", "csrc")
+    assert not any(os.path.exists(os.path.join(csrc, f)) for f in gen.GENERATED)
+    assert not any(os.path.basename(s) in gen.GENERATED for s in build.SOURCES)
+    assert {os.path.basename(s) for s in build.SOURCES} >= {"api.hip", "kmv_host.hip", "pcg.hip"}
+
+
 def test_tile_sources_avoid_packed_fp32_ops():
     """Packed FP32 VALU instructions are disabled in the build flags and never
     written by hand."""
