@@ -448,6 +448,15 @@ void nys_clear_tiles(void);
  * of range or a null output. */
 int32_t nys_plan_chunks(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *tm, int32_t *tail_tm);
 
+/* Host-only query of how the same product splits its column points into ranges,
+ * each summed in its own accumulator and the ranges added in float64: *ranges gets
+ * their number and *points the column points of each (the last one may hold fewer).
+ * The low-precision products take ranges of at most 16384 points, fewer and longer
+ * ones where the range sums of an n x m product would exceed 32 GiB; the float64
+ * products split only to fill the GPU.  No device work, no allocation.  Returns
+ * NYS_EINVAL as nys_plan_chunks does. */
+int32_t nys_plan_ranges(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *ranges, int64_t *points);
+
 /* ---- ceiling probes --------------------------------------------------------
  * nys_peak_probe times one synthetic kernel that keeps a single unit of the GPU
  * busy, so that the rates of the kernel product can be set against what the chip

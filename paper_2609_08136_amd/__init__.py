@@ -30,7 +30,8 @@ OK, NOT_CONVERGED, EINVAL, ENOTPD, ENUMERIC, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4
 EXPORTS = ("nys_workspace_bytes", "kernel_matvec", "kernel_dot", "nys_test_matrix", "nys_sketch", "nys_precond_build",
            "nys_precond_adaptive",
            "nys_precond_apply", "nyspcg_solve", "nyspcg_backward", "nys_autotune", "nys_set_tile",
-           "nys_clear_tiles", "nys_plan_chunks", "nys_peak_probe", "nys_ridge_sketch", "nys_ridge_solve",
+           "nys_clear_tiles", "nys_plan_chunks", "nys_plan_ranges", "nys_peak_probe", "nys_ridge_sketch",
+           "nys_ridge_solve",
            "nys_admm_elastic_net", "nys_last_error", "nys_version")
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -127,6 +128,7 @@ def load(path: str | None = None):
     lib.nys_clear_tiles.argtypes = []
     lib.nys_clear_tiles.restype = None
     lib.nys_plan_chunks.argtypes = [c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]
+    lib.nys_plan_ranges.argtypes = [c_i32, c_i64, c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64)]
     lib.nys_peak_probe.argtypes = [c_i32, c_i32, ctypes.POINTER(c_f64), c_vp, c_sz, c_vp]
     lib.nys_ridge_sketch.argtypes = [c_vp, c_i64, c_i64, c_vp, ctypes.c_uint64, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]
     lib.nys_admm_elastic_net.argtypes = [c_vp, c_i64, c_i64, c_vp, c_f64, c_f64, c_f64, c_f64,
@@ -137,7 +139,7 @@ def load(path: str | None = None):
                                     ctypes.POINTER(NysColInfo), c_vp, c_sz, c_vp]
     for name in ("kernel_matvec", "kernel_dot", "nys_test_matrix", "nys_sketch", "nys_precond_adaptive", "nys_precond_build", "nys_precond_apply", "nyspcg_solve",
                  "nyspcg_backward", "nys_workspace_bytes", "nys_autotune", "nys_set_tile", "nys_plan_chunks",
-                 "nys_peak_probe"):
+                 "nys_plan_ranges", "nys_peak_probe"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     _lib_file = p
@@ -575,6 +577,15 @@ def nys_plan_chunks(prec: int, n: int, d: int, m: int) -> tuple[int, int]:
     tm, tail = c_i32(0), c_i32(0)
     _check(load().nys_plan_chunks(prec, n, d, m, ctypes.byref(tm), ctypes.byref(tail)))
     return tm.value, tail.value
+
+
+def nys_plan_ranges(prec: int, n: int, d: int, m: int) -> tuple[int, int]:
+    """(number of column-point ranges, points per range) of an n x n product with m
+    columns: each range is summed in its own accumulator, the ranges in float64.
+    Host only."""
+    ranges, points = c_i32(0), c_i64(0)
+    _check(load().nys_plan_ranges(prec, n, d, m, ctypes.byref(ranges), ctypes.byref(points)))
+    return ranges.value, points.value
 
 
 PROBE_BF16_MFMA, PROBE_F16_MFMA, PROBE_F64_MFMA, PROBE_EXP2, PROBE_COPY = range(5)

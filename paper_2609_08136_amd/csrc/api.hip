@@ -1031,6 +1031,18 @@ int32_t nys_plan_chunks(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *
   return NYS_OK;
 }
 
+int32_t nys_plan_ranges(int32_t prec, int64_t n, int32_t d, int32_t m, int32_t *ranges, int64_t *points) {
+  if (!valid_prec(prec)) return einval("unsupported precision");
+  if (n < 1 || m < 1) return einval("need n >= 1 and m >= 1");
+  if (d < 1 || d > max_dim(prec)) return einval("d out of range for this precision");
+  if (!ranges || !points) return einval("null pointer");
+  const KmvPlan p = kmv_plan(n, n, m, prec, packed_kp(d, prec));
+  const int64_t tj = p.path == 0 ? 64 : 32;   // column points per tile of the plan's path
+  *ranges = p.splits;
+  *points = std::min<int64_t>((int64_t)p.jsteps * tj, n);
+  return NYS_OK;
+}
+
 int32_t nys_autotune(nys_kernel k, int32_t prec, const double *X, int64_t n, int64_t n_rows, int32_t d,
                      int32_t m, int32_t m_lo, int32_t reps, nys_tile_choice *best, void *ws, size_t ws_bytes,
                      void *stream) {

@@ -232,6 +232,33 @@ def test_plan_chunks_last_chunk_and_float64_costs(lib):
             assert full * tm + (tail or tm) >= m
 
 
+def test_plan_ranges_bound_the_float32_accumulation(lib):
+    """The low-precision products sum at most 16384 column points per float32
+    accumulator where the range sums (n x m x 4 bytes per range) fit in 32 GiB, and
+    fewer, longer ranges where they would not; the float64 products split only to fill
+    the GPU (host logic only)."""
+    n, d, cap = 1_000_000, 16, 32 << 30
+    # the headline's product at n = 1e6: 16 ranges at 512 columns (capped), 62 below
+    assert nys.nys_plan_ranges(nys.F16X3_D6, n, d, 512) == (16, 62528)
+    assert nys.nys_plan_ranges(nys.F16X3_D6, n, d, 128) == (62, 16160)
+    assert nys.nys_plan_ranges(nys.F16X3_D6, n, d, 1) == (62, 16160)
+    assert nys.nys_plan_ranges(nys.FP64, n, d, 512)[0] == 1
+    for prec in (nys.F16X3_D6, nys.F16X3_D10, nys.BF16X3, nys.BF16X3_D6, nys.FP32):
+        for nn in (1000, 20_000, 200_000, n):
+            for m in (1, 16, 64, 128, 256, 512, 2048):
+                ranges, points = nys.nys_plan_ranges(prec, nn, d, m)
+                assert ranges >= 1 and ranges * points >= nn and (ranges - 1) * points < nn
+                wanted = -(-nn // 16384)
+                if wanted * nn * m * 4 <= cap:
+                    assert points <= 16384, (prec, nn, m, ranges, points)
+                else:
+                    assert ranges * nn * m * 4 <= cap
+    rng, pts = ctypes.c_int32(), ctypes.c_int64()
+    assert lib.nys_plan_ranges(9, n, d, 8, ctypes.byref(rng), ctypes.byref(pts)) == nys.EINVAL
+    assert lib.nys_plan_ranges(nys.F16X3_D6, n, 42, 8, ctypes.byref(rng), ctypes.byref(pts)) == nys.EINVAL
+    assert lib.nys_plan_ranges(nys.F16X3_D6, n, d, 8, None, ctypes.byref(pts)) == nys.EINVAL
+
+
 def test_plan_chunks_follow_tuned_widths_and_reject_bad_arguments(lib):
     try:
         nys.nys_set_tile(nys.F16X3_D10, 257, 512, 128)
